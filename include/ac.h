@@ -1,0 +1,200 @@
+/*
+ * ac.h -- C ABI of the MI355X (gfx950) Aho-Corasick scan library, libac.so.
+ *
+ * The library finds every occurrence of a set of byte patterns in a byte
+ * text, the multiple-string-matching problem of the paper (abstract, Sec. I).
+ * It does so the way the paper's Sec. II splits the method: a host step that
+ * constructs the string-matching machine (ac_build), and a device step that
+ * processes the text with it in one pass (ac_scan).
+ *
+ * Result convention (shared by every scan entry point):
+ *   a match is the 64-bit key (e << 32) | k, meaning pattern k (its 0-based
+ *   index in the list given to ac_build) ends at 0-based text position e.
+ *   Every occurrence is reported, including overlapping ones and patterns
+ *   nested inside others (the Sec. IV.A example reports both SHE and HE).
+ *   Duplicate patterns each report their own id. Keys are written in an
+ *   unspecified order; sorted ascending they give the list ordered by
+ *   (e, k). Texts must be shorter than 2^32 bytes.
+ *
+ * Memory: texts, match buffers and counters passed to scans are device
+ * pointers owned by the caller. The automaton owns its host and device
+ * tables until ac_free. Streams are hipStream_t values passed as void*;
+ * NULL means the default stream. Calls never throw; they return AC_OK or a
+ * negative AC_ERR_* code and leave a message for ac_last_error().
+ */
+#ifndef AC_H
+#define AC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    AC_OK = 0,
+    AC_ERR_INVALID = -1,   /* bad argument: null pointer, empty pattern, misaligned text */
+    AC_ERR_NOMEM = -2,     /* host or device allocation failed */
+    AC_ERR_TOO_LARGE = -3, /* machine or text beyond the index ranges below */
+    AC_ERR_OVERFLOW = -4,  /* more matches than the buffer holds (ac_scan_sync) */
+    AC_ERR_HIP = -5,       /* a HIP runtime call failed */
+    AC_ERR_BUSY = -6       /* resource budget exhausted (serving) */
+};
+
+/* Where the transition table lives during a scan. */
+enum {
+    AC_PLACE_AUTO = 0,   /* LDS_FULL if the table fits a workgroup's LDS, else LDS_HOT */
+    AC_PLACE_GLOBAL = 1, /* every lookup from global memory (L2 / MALL resident) */
+    AC_PLACE_LDS_FULL = 2, /* the whole 32-bit table copied into LDS */
+    AC_PLACE_LDS_HOT = 3   /* 16-bit rows of the most visited states in LDS, rest global */
+};
+
+/* Which device matcher a scan runs. */
+enum {
+    AC_ALGO_DFA = 0, /* failure transitions folded into a full DFA, walked over
+                        overlapping chunks of the text */
+    AC_ALGO_PFAC = 1 /* failure-less machine, one walk per start position */
+};
+
+typedef struct ac_automaton ac_automaton;
+
+typedef struct {
+    uint32_t placement;   /* AC_PLACE_*; default AC_PLACE_AUTO */
+    uint32_t hot_states;  /* cap on states in the LDS_HOT image; 0 = as many as fit */
+    uint32_t lds_bytes;   /* LDS budget for the table image; 0 = 160 KiB less 2 KiB */
+    uint32_t reserved;
+} ac_build_opts;
+
+typedef struct {
+    uint64_t n_states;     /* states of the machine (trie nodes, root = 0) */
+    uint32_t n_patterns;
+    uint32_t sigma;        /* distinct bytes that occur in the patterns */
+    uint32_t n_cols;       /* columns of the transition tables (>= sigma) */
+    uint32_t m_max;        /* longest pattern, bytes */
+    uint32_t placement;    /* resolved AC_PLACE_* used by AUTO scans */
+    uint32_t hot_states;   /* rows in the LDS_HOT image (0 if none) */
+    uint32_t class_shift;  /* byte -> column is (b >> shift) & (n_cols-1) when */
+    uint32_t class_hashed; /*   class_hashed is 1; else a 256-entry map */
+    uint64_t table_bytes;  /* device bytes of the DFA table */
+    uint64_t out_entries;  /* total entries of all output sets */
+    double build_ms;       /* host time spent constructing the machine */
+} ac_info_t;
+
+/*
+ * ac_build -- construct the machine for n_patterns patterns (Sec. II, step 1;
+ * Sec. II.A for goto / failure / output functions; Sec. III for folding the
+ * failure transitions into ordinary ones, giving a full DFA) and upload its
+ * tables to the current device on `stream` (synchronised before return).
+ *
+ *   pat_bytes  host, concatenated pattern bytes
+ *   pat_off    host, n_patterns + 1 non-decreasing offsets: pattern k is
+ *              pat_bytes[pat_off[k] .. pat_off[k+1])
+ *   opts       NULL for defaults
+ *   out        receives the handle; free with ac_free
+ *
+ * Errors: AC_ERR_INVALID for n_patterns == 0, a null pointer, an empty
+ * pattern or decreasing offsets; AC_ERR_TOO_LARGE if the table would need
+ * 2^31 or more entries or the output sets 2^32 or more; AC_ERR_NOMEM,
+ * AC_ERR_HIP.
+ */
+int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patterns,
+             const ac_build_opts *opts, void *stream, ac_automaton **out);
+
+/*
+ * ac_build_host -- the same construction as ac_build, kept on the host only
+ * (no device is touched; ac_scan rejects the result). For inspecting the
+ * tables with ac_get_table. Errors as ac_build, minus AC_ERR_HIP.
+ */
+int ac_build_host(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patterns,
+                  const ac_build_opts *opts, ac_automaton **out);
+
+/* Host tables of an automaton, in the library's state numbering (root = 0). */
+enum {
+    AC_TABLE_DFA = 0,     /* uint32 [n_states][n_cols]: successor | 1<<31 if it is final */
+    AC_TABLE_GO = 1,      /* uint32 [n_states][n_cols]: goto child | 1<<31 if it ends a
+                             pattern itself, 0 = no edge */
+    AC_TABLE_OUT_OFF = 2, /* uint32 [n_states+1]: output set s = OUT_IDS[off[s] .. off[s+1]) */
+    AC_TABLE_OUT_IDS = 3, /* uint32: pattern ids, ascending within each set */
+    AC_TABLE_OWN_OFF = 4, /* uint32 [n_states+1]: patterns ending exactly at s */
+    AC_TABLE_OWN_IDS = 5, /* uint32 */
+    AC_TABLE_HOT_DFA = 6, /* uint16 [hot_states][n_cols]: DFA rows of the LDS image,
+                             successor | 1<<15 if final */
+    AC_TABLE_HOT_GO = 7,  /* uint16 [hot_states][n_cols]: goto rows of the LDS image */
+    AC_TABLE_CMAP = 8     /* uint8 [256]: byte -> column, 255 = byte in no pattern */
+};
+
+/*
+ * ac_get_table -- copy host table `which` (AC_TABLE_*) into dst (host,
+ * dst_bytes long) and store its size in *bytes. dst == NULL only queries
+ * the size. Errors: AC_ERR_INVALID for an unknown table, a NULL automaton or
+ * size pointer, or a destination that is too small.
+ */
+int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_bytes,
+                 uint64_t *bytes);
+
+/* ac_free -- release the automaton and its device tables. NULL is a no-op.
+ * The caller must ensure no scan using it is still running. */
+void ac_free(ac_automaton *a);
+
+/* ac_info -- sizes and choices of a built automaton. */
+int ac_info(const ac_automaton *a, ac_info_t *info);
+
+typedef struct {
+    uint32_t algo;      /* AC_ALGO_DFA (default) or AC_ALGO_PFAC */
+    uint32_t chunk;     /* DFA: text bytes owned by one walker; multiple of 16;
+                           0 = chosen from the text length */
+    uint32_t block;     /* threads per workgroup, multiple of 64, <= 1024; 0 = auto */
+    uint32_t placement; /* 0 = the automaton's; else an AC_PLACE_* override */
+} ac_scan_opts;
+
+/*
+ * ac_scan -- process the text with the machine in one pass (Sec. II, step 2)
+ * and append every match to d_matches. Asynchronous on `stream`.
+ *
+ * With AC_ALGO_DFA the text is split into chunks of `chunk` bytes; the walker
+ * of chunk [kC, kC + C) starts max(0, kC - m_max + 1) bytes in (rounded down
+ * to 16) from the root and reports only matches ending inside its chunk, so
+ * every occurrence is reported exactly once. With AC_ALGO_PFAC every start
+ * position gets its own failure-less walk (Sec. II.B, Sec. IV.A).
+ *
+ *   d_text     device, n bytes, 16-byte aligned (n == 0 allowed)
+ *   d_matches  device, room for `capacity` uint64 keys
+ *   d_count    device uint64; set to the total number of matches, even when
+ *              it exceeds capacity (only the first `capacity` keys written)
+ *   opts       NULL for defaults
+ *
+ * Errors (checked before anything is queued): AC_ERR_INVALID for null
+ * pointers, a misaligned text or bad options; AC_ERR_TOO_LARGE for
+ * n >= 2^32; AC_ERR_HIP if a launch fails. Overflow is not an error here:
+ * compare *d_count with capacity, or use ac_scan_sync.
+ */
+int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_matches,
+            uint64_t capacity, uint64_t *d_count, const ac_scan_opts *opts, void *stream);
+
+/*
+ * ac_scan_sync -- ac_scan, then wait for `stream` and copy the total count to
+ * *h_count. Returns AC_ERR_OVERFLOW if the total exceeds capacity (the first
+ * `capacity` keys are still valid).
+ */
+int ac_scan_sync(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_matches,
+                 uint64_t capacity, uint64_t *d_count, const ac_scan_opts *opts, void *stream,
+                 uint64_t *h_count);
+
+/*
+ * ac_sort_matches -- sort `count` keys in place, ascending, on `stream`,
+ * giving the canonical (e, k) order. d_tmp is device scratch of at least
+ * ac_sort_scratch_bytes(count) bytes, owned by the caller.
+ * Errors: AC_ERR_INVALID for null pointers or too small scratch.
+ */
+uint64_t ac_sort_scratch_bytes(uint64_t count);
+int ac_sort_matches(uint64_t *d_keys, uint64_t count, void *d_tmp, uint64_t tmp_bytes,
+                    void *stream);
+
+/* ac_last_error -- message of the last failing call on this thread ("" if none). */
+const char *ac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AC_H */

@@ -1,0 +1,278 @@
+"""ctypes binding of libac.so (include/ac.h), one Python function per C entry point.
+
+Arguments are marshalled only: device buffers may be torch tensors (their
+``data_ptr()``) or integer addresses, streams may be ``torch.cuda.Stream``
+objects, raw integer handles or None (torch's current stream). Every step of
+the scan runs in the library's HIP kernels; there is no Python or CPU path.
+A failing call raises ``AcError`` carrying the library's status and message.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # torch's HIP runtime must be the one libac.so binds to: load it first
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libac.so")
+
+AC_OK = 0
+AC_ERR_INVALID = -1
+AC_ERR_NOMEM = -2
+AC_ERR_TOO_LARGE = -3
+AC_ERR_OVERFLOW = -4
+AC_ERR_HIP = -5
+AC_ERR_BUSY = -6
+
+AC_PLACE_AUTO = 0
+AC_PLACE_GLOBAL = 1
+AC_PLACE_LDS_FULL = 2
+AC_PLACE_LDS_HOT = 3
+
+AC_ALGO_DFA = 0
+AC_ALGO_PFAC = 1
+
+AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
+    AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP = range(9)
+
+_TABLE_DTYPE = {AC_TABLE_HOT_DFA: np.uint16, AC_TABLE_HOT_GO: np.uint16, AC_TABLE_CMAP: np.uint8}
+
+
+class AcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+        self.message = message
+
+
+class ac_build_opts(ctypes.Structure):
+    _fields_ = [("placement", ctypes.c_uint32), ("hot_states", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ac_info_t(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_uint64), ("n_patterns", ctypes.c_uint32),
+                ("sigma", ctypes.c_uint32), ("n_cols", ctypes.c_uint32),
+                ("m_max", ctypes.c_uint32), ("placement", ctypes.c_uint32),
+                ("hot_states", ctypes.c_uint32), ("class_shift", ctypes.c_uint32),
+                ("class_hashed", ctypes.c_uint32), ("table_bytes", ctypes.c_uint64),
+                ("out_entries", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
+
+
+class ac_scan_opts(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("block", ctypes.c_uint32), ("placement", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+
+# name -> (restype, argtypes); every symbol include/ac.h declares
+SIGNATURES = {
+    "ac_build": (ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(ac_build_opts), _vp,
+                                ctypes.POINTER(_vp)]),
+    "ac_build_host": (ctypes.c_int, [_vp, _vp, _u32, ctypes.POINTER(ac_build_opts),
+                                     ctypes.POINTER(_vp)]),
+    "ac_get_table": (ctypes.c_int, [_vp, _u32, _vp, _u64, ctypes.POINTER(_u64)]),
+    "ac_free": (None, [_vp]),
+    "ac_info": (ctypes.c_int, [_vp, ctypes.POINTER(ac_info_t)]),
+    "ac_scan": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, ctypes.POINTER(ac_scan_opts), _vp]),
+    "ac_scan_sync": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, ctypes.POINTER(ac_scan_opts),
+                                    _vp, ctypes.POINTER(_u64)]),
+    "ac_sort_scratch_bytes": (_u64, [_u64]),
+    "ac_sort_matches": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp]),
+    "ac_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libac.so (raising if it is not built) and declare its signatures."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
+                              "`python -m paper_1403_1305_amd.build_lib` (or __graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != AC_OK:
+        raise AcError(rc, (_lib.ac_last_error() or b"").decode())
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return int(x)
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    if isinstance(s, torch.cuda.Stream):
+        return s.cuda_stream
+    return int(s)
+
+
+def patterns_csr(patterns) -> tuple[np.ndarray, np.ndarray]:
+    """Concatenated pattern bytes (uint8) and n+1 offsets (uint64)."""
+    pats = [bytes(p) for p in patterns]
+    off = np.zeros(len(pats) + 1, dtype=np.uint64)
+    if pats:
+        off[1:] = np.cumsum([len(p) for p in pats], dtype=np.uint64)
+    data = np.frombuffer(b"".join(pats) or b"\0", dtype=np.uint8).copy()
+    return data, off
+
+
+class Automaton:
+    """Owning handle of an ac_automaton*; freed with ac_free."""
+
+    def __init__(self, handle: int, on_device: bool):
+        self.handle = handle
+        self.on_device = on_device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ac_free(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return ctypes.c_void_p(self.handle)
+
+
+def _opts(placement=AC_PLACE_AUTO, hot_states=0, lds_bytes=0):
+    return ac_build_opts(placement, hot_states, lds_bytes, 0)
+
+
+def ac_build(pat_bytes, pat_off, n_patterns: int | None = None, opts: ac_build_opts | None = None,
+             stream=None) -> Automaton:
+    lib = load_library()
+    pat_bytes = np.ascontiguousarray(pat_bytes, dtype=np.uint8)
+    pat_off = np.ascontiguousarray(pat_off, dtype=np.uint64)
+    n = len(pat_off) - 1 if n_patterns is None else n_patterns
+    h = _vp()
+    _check(lib.ac_build(pat_bytes.ctypes.data, pat_off.ctypes.data, n,
+                        ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                        ctypes.byref(h)))
+    return Automaton(h.value, True)
+
+
+def ac_build_host(pat_bytes, pat_off, n_patterns: int | None = None,
+                  opts: ac_build_opts | None = None) -> Automaton:
+    lib = load_library()
+    pat_bytes = np.ascontiguousarray(pat_bytes, dtype=np.uint8)
+    pat_off = np.ascontiguousarray(pat_off, dtype=np.uint64)
+    n = len(pat_off) - 1 if n_patterns is None else n_patterns
+    h = _vp()
+    _check(lib.ac_build_host(pat_bytes.ctypes.data, pat_off.ctypes.data, n,
+                             ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
+    return Automaton(h.value, False)
+
+
+def ac_free(a: Automaton):
+    if a.handle:
+        load_library().ac_free(a.handle)
+        a.handle = None
+
+
+def ac_info(a: Automaton) -> dict:
+    info = ac_info_t()
+    _check(load_library().ac_info(a.handle, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in ac_info_t._fields_}
+
+
+def ac_get_table(a: Automaton, which: int) -> np.ndarray:
+    lib = load_library()
+    size = _u64()
+    _check(lib.ac_get_table(a.handle, which, None, 0, ctypes.byref(size)))
+    dt = _TABLE_DTYPE.get(which, np.uint32)
+    out = np.zeros(max(1, size.value // np.dtype(dt).itemsize), dtype=dt)
+    _check(lib.ac_get_table(a.handle, which, out.ctypes.data, out.nbytes, ctypes.byref(size)))
+    return out[: size.value // np.dtype(dt).itemsize]
+
+
+def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0):
+    return ac_scan_opts(algo, chunk, block, placement)
+
+
+def ac_scan(a: Automaton, d_text, n: int, d_matches, capacity: int, d_count,
+            opts: ac_scan_opts | None = None, stream=None) -> None:
+    _check(load_library().ac_scan(a.handle, _ptr(d_text), n, _ptr(d_matches), capacity,
+                                  _ptr(d_count), ctypes.byref(opts) if opts is not None else None,
+                                  _stream(stream)))
+
+
+def ac_scan_sync(a: Automaton, d_text, n: int, d_matches, capacity: int, d_count,
+                 opts: ac_scan_opts | None = None, stream=None) -> int:
+    """Returns the total match count; raises AcError(AC_ERR_OVERFLOW) if it
+    exceeds capacity (the error carries the count in its message)."""
+    h = _u64()
+    _check(load_library().ac_scan_sync(a.handle, _ptr(d_text), n, _ptr(d_matches), capacity,
+                                       _ptr(d_count),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def ac_sort_scratch_bytes(count: int) -> int:
+    return load_library().ac_sort_scratch_bytes(count)
+
+
+def ac_sort_matches(d_keys, count: int, d_tmp, tmp_bytes: int, stream=None) -> None:
+    _check(load_library().ac_sort_matches(_ptr(d_keys), count, _ptr(d_tmp), tmp_bytes,
+                                          _stream(stream)))
+
+
+def ac_last_error() -> str:
+    return (load_library().ac_last_error() or b"").decode()
+
+
+# ---------------------------------------------------------------- conveniences
+
+def scan_text(a: Automaton, d_text: torch.Tensor, capacity: int | None = None,
+              opts: ac_scan_opts | None = None, stream=None) -> torch.Tensor:
+    """Scan a 1-D uint8 device tensor; returns the match keys as an int64
+    device tensor (bit pattern of the uint64 keys), in unspecified order. The
+    output buffer is sized by ``capacity`` and regrown once on overflow."""
+    n = d_text.numel()
+    dev = d_text.device
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = capacity if capacity is not None else max(1024, n // 256)
+    for _ in range(2):
+        out = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
+        try:
+            total = ac_scan_sync(a, d_text, n, out, cap, count, opts, stream)
+            return out[:total]
+        except AcError as e:
+            if e.status != AC_ERR_OVERFLOW:
+                raise
+            cap = int(count.item())
+    raise AcError(AC_ERR_OVERFLOW, "match count changed between two scans")
+
+
+def sort_keys(keys: torch.Tensor, stream=None) -> torch.Tensor:
+    """Sort int64-stored uint64 keys ascending in place on the device."""
+    n = keys.numel()
+    if n > 1:
+        tmp = torch.empty(ac_sort_scratch_bytes(n), dtype=torch.uint8, device=keys.device)
+        ac_sort_matches(keys, n, tmp, tmp.numel(), stream)
+    return keys
+
+
+def keys_to_numpy(keys: torch.Tensor) -> np.ndarray:
+    return keys.cpu().numpy().view(np.uint64)

@@ -1,0 +1,277 @@
+// api.hip -- the extern "C" surface declared in include/ac.h.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/ac.h"
+#include "machine.h"
+#include "scan.h"
+
+struct ac_automaton {
+    acm::Machine m;
+    acm::DeviceMachine dm;
+    bool on_device = false;
+    int device = -1;
+    uint32_t placement = AC_PLACE_GLOBAL;  // resolved default for scans
+    std::vector<void *> allocations;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+// Largest LDS image, in bytes, a build may plan for.
+uint32_t lds_budget(const ac_build_opts *o) {
+    const uint32_t dflt = acm::kLdsPerWorkgroup - 2048;
+    if (!o || o->lds_bytes == 0) return dflt;
+    return std::min(o->lds_bytes, dflt);
+}
+
+template <typename T>
+int upload(ac_automaton *a, const std::vector<T> &v, const T **dst, hipStream_t stream) {
+    *dst = nullptr;
+    if (v.empty()) return AC_OK;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, v.size() * sizeof(T));
+    if (e != hipSuccess) return fail(AC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    a->allocations.push_back(p);
+    e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(AC_ERR_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    *dst = static_cast<const T *>(p);
+    return AC_OK;
+}
+
+void release(ac_automaton *a) {
+    for (void *p : a->allocations) (void)hipFree(p);
+    a->allocations.clear();
+}
+
+int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_build_opts *opts,
+                 ac_automaton **out, ac_automaton *&a) {
+    if (!out) return fail(AC_ERR_INVALID, "ac_build: out is NULL");
+    *out = nullptr;
+    const uint32_t place = opts ? opts->placement : AC_PLACE_AUTO;
+    if (place > AC_PLACE_LDS_HOT) return fail(AC_ERR_INVALID, "ac_build: unknown placement");
+    a = new (std::nothrow) ac_automaton();
+    if (!a) return fail(AC_ERR_NOMEM, "ac_build: out of host memory");
+    const uint32_t budget = lds_budget(opts);
+    acm::HotPlan plan;
+    if (place == AC_PLACE_AUTO || place == AC_PLACE_LDS_HOT) {
+        plan.lds_bytes = budget;
+        plan.max_states = opts ? opts->hot_states : 0;
+        plan.only_if_needed = place == AC_PLACE_AUTO;
+    }
+    std::string err;
+    int rc;
+    try {
+        rc = acm::build_machine(pat, off, n, plan, a->m, err);
+    } catch (const std::bad_alloc &) {
+        rc = AC_ERR_NOMEM;
+        err = "ac_build: out of host memory";
+    }
+    if (rc != AC_OK) {
+        delete a;
+        a = nullptr;
+        return fail(rc, err);
+    }
+    const uint64_t full = 256ull + uint64_t(a->m.n_states) * a->m.n_cols * 4ull;
+    if (place == AC_PLACE_LDS_FULL && full > budget) {
+        delete a;
+        a = nullptr;
+        return fail(AC_ERR_TOO_LARGE, "ac_build: table does not fit the LDS (placement LDS_FULL)");
+    }
+    if (place == AC_PLACE_AUTO)
+        a->placement = full <= budget ? AC_PLACE_LDS_FULL
+                                      : (a->m.hot_states > 0 ? AC_PLACE_LDS_HOT : AC_PLACE_GLOBAL);
+    else
+        a->placement = place;
+    if (a->placement == AC_PLACE_LDS_HOT && a->m.hot_states == 0) a->placement = AC_PLACE_GLOBAL;
+    return AC_OK;
+}
+
+bool resolve_placement(const ac_automaton *a, uint32_t want, uint32_t &place) {
+    place = want == AC_PLACE_AUTO ? a->placement : want;
+    if (place == AC_PLACE_LDS_HOT && a->m.hot_states == 0) return false;
+    if (place == AC_PLACE_LDS_FULL &&
+        256ull + uint64_t(a->m.n_states) * a->m.n_cols * 4ull > acm::kLdsPerWorkgroup)
+        return false;
+    return place <= AC_PLACE_LDS_HOT;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ac_last_error(void) { return g_err.c_str(); }
+
+int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patterns,
+             const ac_build_opts *opts, void *stream, ac_automaton **out) {
+    ac_automaton *a = nullptr;
+    int rc = build_common(pat_bytes, pat_off, n_patterns, opts, out, a);
+    if (rc != AC_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        delete a;
+        return fail(AC_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    a->device = dev;
+    acm::DeviceMachine &dm = a->dm;
+    const acm::Machine &m = a->m;
+    dm.n_states = m.n_states;
+    dm.n_cols = m.n_cols;
+    dm.m_max = m.m_max;
+    dm.hot_states = m.hot_states;
+    dm.log2_cols = m.log2_cols;
+    dm.cols_pow2 = m.cols_pow2;
+    dm.hashed = m.hashed;
+    dm.hash_shift = m.hash_shift;
+    std::memcpy(dm.hash_letter, m.hash_letter, sizeof(dm.hash_letter));
+    std::vector<uint8_t> cmap(m.cmap, m.cmap + 256);
+    if ((rc = upload(a, m.dfa, &dm.dfa, s)) || (rc = upload(a, m.go, &dm.go, s)) ||
+        (rc = upload(a, m.out_off, &dm.out_off, s)) || (rc = upload(a, m.out_ids, &dm.out_ids, s)) ||
+        (rc = upload(a, m.own_off, &dm.own_off, s)) || (rc = upload(a, m.own_ids, &dm.own_ids, s)) ||
+        (rc = upload(a, m.hot_dfa, &dm.hot_dfa, s)) || (rc = upload(a, m.hot_go, &dm.hot_go, s)) ||
+        (rc = upload(a, cmap, &dm.cmap, s))) {
+        (void)hipStreamSynchronize(s);
+        release(a);
+        delete a;
+        return rc;
+    }
+    // out_ids may be empty only if no pattern exists, which build rejects
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release(a);
+        delete a;
+        return fail(AC_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    }
+    a->on_device = true;
+    *out = a;
+    return AC_OK;
+}
+
+int ac_build_host(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patterns,
+                  const ac_build_opts *opts, ac_automaton **out) {
+    ac_automaton *a = nullptr;
+    int rc = build_common(pat_bytes, pat_off, n_patterns, opts, out, a);
+    if (rc != AC_OK) return rc;
+    *out = a;
+    return AC_OK;
+}
+
+void ac_free(ac_automaton *a) {
+    if (!a) return;
+    release(a);
+    delete a;
+}
+
+int ac_info(const ac_automaton *a, ac_info_t *info) {
+    if (!a || !info) return fail(AC_ERR_INVALID, "ac_info: NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_states = a->m.n_states;
+    info->n_patterns = a->m.n_patterns;
+    info->sigma = a->m.sigma;
+    info->n_cols = a->m.n_cols;
+    info->m_max = a->m.m_max;
+    info->placement = a->placement;
+    info->hot_states = a->m.hot_states;
+    info->class_shift = a->m.hash_shift;
+    info->class_hashed = a->m.hashed ? 1u : 0u;
+    info->table_bytes = uint64_t(a->m.n_states) * a->m.n_cols * 4ull;
+    info->out_entries = a->m.out_ids.size();
+    info->build_ms = a->m.build_ms;
+    return AC_OK;
+}
+
+int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_bytes,
+                 uint64_t *bytes) {
+    if (!a || !bytes) return fail(AC_ERR_INVALID, "ac_get_table: NULL argument");
+    const void *src = nullptr;
+    uint64_t sz = 0;
+    const acm::Machine &m = a->m;
+    switch (which) {
+        case AC_TABLE_DFA: src = m.dfa.data(); sz = m.dfa.size() * 4; break;
+        case AC_TABLE_GO: src = m.go.data(); sz = m.go.size() * 4; break;
+        case AC_TABLE_OUT_OFF: src = m.out_off.data(); sz = m.out_off.size() * 4; break;
+        case AC_TABLE_OUT_IDS: src = m.out_ids.data(); sz = m.out_ids.size() * 4; break;
+        case AC_TABLE_OWN_OFF: src = m.own_off.data(); sz = m.own_off.size() * 4; break;
+        case AC_TABLE_OWN_IDS: src = m.own_ids.data(); sz = m.own_ids.size() * 4; break;
+        case AC_TABLE_HOT_DFA: src = m.hot_dfa.data(); sz = m.hot_dfa.size() * 2; break;
+        case AC_TABLE_HOT_GO: src = m.hot_go.data(); sz = m.hot_go.size() * 2; break;
+        case AC_TABLE_CMAP: src = m.cmap; sz = 256; break;
+        default: return fail(AC_ERR_INVALID, "ac_get_table: unknown table");
+    }
+    *bytes = sz;
+    if (!dst) return AC_OK;
+    if (dst_bytes < sz) return fail(AC_ERR_INVALID, "ac_get_table: destination too small");
+    if (sz) std::memcpy(dst, src, sz);
+    return AC_OK;
+}
+
+int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_matches,
+            uint64_t capacity, uint64_t *d_count, const ac_scan_opts *opts, void *stream) {
+    if (!a || !d_count) return fail(AC_ERR_INVALID, "ac_scan: NULL automaton or count");
+    if (!a->on_device) return fail(AC_ERR_INVALID, "ac_scan: automaton has no device tables");
+    if (n > 0 && !d_text) return fail(AC_ERR_INVALID, "ac_scan: NULL text");
+    if (capacity > 0 && !d_matches) return fail(AC_ERR_INVALID, "ac_scan: NULL match buffer");
+    if (n >= (1ull << 32)) return fail(AC_ERR_TOO_LARGE, "ac_scan: text of 2^32 bytes or more");
+    if (n > 0 && (reinterpret_cast<uintptr_t>(d_text) & 15u))
+        return fail(AC_ERR_INVALID, "ac_scan: text must be 16-byte aligned");
+    acm::ScanConfig cfg;
+    uint32_t want = AC_PLACE_AUTO;
+    if (opts) {
+        cfg.algo = opts->algo;
+        cfg.chunk = opts->chunk;
+        cfg.block = opts->block;
+        want = opts->placement;
+    }
+    if (cfg.algo > AC_ALGO_PFAC) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
+    if (!resolve_placement(a, want, cfg.placement))
+        return fail(AC_ERR_INVALID, "ac_scan: placement not available for this automaton");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != a->device) return fail(AC_ERR_INVALID, "ac_scan: automaton lives on another device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::string err;
+    int rc = acm::launch_zero_count(d_count, s, err);
+    if (rc == AC_OK) {
+        rc = cfg.algo == AC_ALGO_DFA
+                 ? acm::launch_dfa_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err)
+                 : acm::launch_pfac_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
+    }
+    return rc == AC_OK ? AC_OK : fail(rc, err);
+}
+
+int ac_scan_sync(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_matches,
+                 uint64_t capacity, uint64_t *d_count, const ac_scan_opts *opts, void *stream,
+                 uint64_t *h_count) {
+    if (!h_count) return fail(AC_ERR_INVALID, "ac_scan_sync: NULL host count");
+    int rc = ac_scan(a, d_text, n, d_matches, capacity, d_count, opts, stream);
+    if (rc != AC_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(h_count, d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(AC_ERR_HIP, std::string("ac_scan_sync: ") + hipGetErrorString(e));
+    if (*h_count > capacity)
+        return fail(AC_ERR_OVERFLOW, "ac_scan_sync: " + std::to_string(*h_count) +
+                                         " matches exceed capacity " + std::to_string(capacity));
+    return AC_OK;
+}
+
+uint64_t ac_sort_scratch_bytes(uint64_t count) { return acm::sort_scratch_bytes(count); }
+
+int ac_sort_matches(uint64_t *d_keys, uint64_t count, void *d_tmp, uint64_t tmp_bytes, void *stream) {
+    if (count > 1 && (!d_keys || !d_tmp)) return fail(AC_ERR_INVALID, "ac_sort_matches: NULL buffer");
+    std::string err;
+    int rc = acm::launch_sort(d_keys, count, d_tmp, tmp_bytes, static_cast<hipStream_t>(stream), err);
+    return rc == AC_OK ? AC_OK : fail(rc, err);
+}
+
+}  // extern "C"

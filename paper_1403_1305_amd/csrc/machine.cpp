@@ -1,0 +1,293 @@
+// machine.cpp -- host construction of the goto / failure / output functions and
+// their full-DFA form (see machine.h).
+#include "machine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "../../include/ac.h"
+
+namespace acm {
+namespace {
+
+uint32_t ceil_log2(uint32_t x) {
+    uint32_t k = 0;
+    while ((1u << k) < x) ++k;
+    return k;
+}
+
+// Byte classes. Bytes that occur in some pattern get a column; all others
+// send every state back to the root (no pattern can continue through them).
+// When the pattern alphabet has at most 8 letters and some window of <= 3
+// consecutive bits tells them apart, the column is that bit field, which the
+// scan kernels compute with a shift and a mask instead of a table lookup.
+void assign_classes(const bool present[256], Machine &m) {
+    uint32_t sigma = 0;
+    for (int b = 0; b < 256; ++b) sigma += present[b];
+    m.sigma = sigma;
+    std::memset(m.cmap, kNoClass, sizeof(m.cmap));
+    if (sigma <= 8) {
+        for (uint32_t k = ceil_log2(sigma); k <= 3 && !m.hashed; ++k) {
+            for (uint32_t sh = 0; sh + k <= 8 && !m.hashed; ++sh) {
+                uint32_t seen = 0;
+                bool ok = true;
+                for (int b = 0; b < 256 && ok; ++b) {
+                    if (!present[b]) continue;
+                    uint32_t h = (uint32_t(b) >> sh) & ((1u << k) - 1);
+                    ok = !(seen & (1u << h));
+                    seen |= 1u << h;
+                }
+                if (!ok) continue;
+                m.hashed = true;
+                m.hash_shift = sh;
+                m.n_cols = 1u << k;
+                for (uint32_t h = 0; h < 8; ++h) {
+                    // a byte that hashes to column h can never equal a letter owned
+                    // by another column; unused columns get such a byte
+                    m.hash_letter[h] = uint8_t(((h ^ 1u) & ((1u << k) - 1)) << sh);
+                    if (k == 0) m.hash_letter[h] = 0;
+                }
+                for (int b = 0; b < 256; ++b)
+                    if (present[b]) {
+                        uint32_t h = (uint32_t(b) >> sh) & ((1u << k) - 1);
+                        m.cmap[b] = uint8_t(h);
+                        m.hash_letter[h] = uint8_t(b);
+                    }
+            }
+        }
+    }
+    if (!m.hashed) {
+        m.n_cols = sigma;
+        uint32_t r = 0;
+        for (int b = 0; b < 256; ++b)
+            if (present[b]) m.cmap[b] = uint8_t(r++);
+    }
+    m.cols_pow2 = (m.n_cols & (m.n_cols - 1)) == 0;
+    m.log2_cols = m.cols_pow2 ? ceil_log2(m.n_cols) : 0;
+}
+
+}  // namespace
+
+int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const HotPlan &plan,
+                  Machine &m, std::string &err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (n == 0 || pat == nullptr || off == nullptr) {
+        err = "ac_build: need at least one pattern and non-null pattern arrays";
+        return AC_ERR_INVALID;
+    }
+    uint64_t total = 0;
+    bool present[256] = {false};
+    m.n_patterns = n;
+    m.m_max = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        if (off[k + 1] <= off[k]) {
+            err = "ac_build: pattern " + std::to_string(k) + " is empty or its offsets decrease";
+            return AC_ERR_INVALID;
+        }
+        uint64_t len = off[k + 1] - off[k];
+        if (len >= (1ull << 31)) {
+            err = "ac_build: pattern longer than 2^31 bytes";
+            return AC_ERR_TOO_LARGE;
+        }
+        total += len;
+        m.m_max = std::max<uint32_t>(m.m_max, uint32_t(len));
+        for (uint64_t i = off[k]; i < off[k + 1]; ++i) present[pat[i]] = true;
+    }
+    if (total + 1 >= (1ull << 31)) {
+        err = "ac_build: more than 2^31 pattern bytes";
+        return AC_ERR_TOO_LARGE;
+    }
+    assign_classes(present, m);
+    const uint32_t C = m.n_cols;
+
+    // ---- goto function: a trie, nodes numbered as they are created
+    std::vector<int32_t> kid;  // node * C + c -> node, -1 if no edge
+    kid.reserve(size_t(std::min<uint64_t>(total + 1, 1u << 24)) * C);
+    kid.assign(C, -1);
+    uint32_t nodes = 1;
+    std::vector<std::pair<uint32_t, uint32_t>> ends;  // (node, pattern id)
+    ends.reserve(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        uint32_t v = 0;
+        for (uint64_t i = off[k]; i < off[k + 1]; ++i) {
+            uint32_t c = m.cmap[pat[i]];
+            int32_t w = kid[size_t(v) * C + c];
+            if (w < 0) {
+                w = int32_t(nodes++);
+                kid[size_t(v) * C + c] = w;
+                kid.resize(size_t(nodes) * C, -1);
+            }
+            v = uint32_t(w);
+        }
+        ends.emplace_back(v, k);
+    }
+    const uint32_t S = nodes;
+    if (uint64_t(S) * C >= (1ull << 31)) {
+        err = "ac_build: transition table would exceed 2^31 entries";
+        return AC_ERR_TOO_LARGE;
+    }
+
+    // ---- breadth-first order (children visited by column)
+    std::vector<uint32_t> order;
+    order.reserve(S);
+    std::vector<uint32_t> bfs(S);
+    order.push_back(0);
+    for (size_t i = 0; i < order.size(); ++i) {
+        uint32_t v = order[i];
+        bfs[v] = uint32_t(i);
+        for (uint32_t c = 0; c < C; ++c) {
+            int32_t w = kid[size_t(v) * C + c];
+            if (w >= 0) order.push_back(uint32_t(w));
+        }
+    }
+    // children in breadth-first ids
+    std::vector<int32_t> child(size_t(S) * C, -1);
+    for (uint32_t v = 0; v < S; ++v)
+        for (uint32_t c = 0; c < C; ++c) {
+            int32_t w = kid[size_t(v) * C + c];
+            if (w >= 0) child[size_t(bfs[v]) * C + c] = int32_t(bfs[w]);
+        }
+    std::vector<int32_t>().swap(kid);
+
+    // ---- failure function and full DFA, row by row in breadth-first order.
+    // A row only reads the row of its failure state, which is shallower and
+    // therefore already final.
+    std::vector<uint32_t> delta(size_t(S) * C);
+    std::vector<uint32_t> fail(S, 0);
+    for (uint32_t c = 0; c < C; ++c) {
+        int32_t w = child[c];
+        delta[c] = w >= 0 ? uint32_t(w) : 0u;
+        if (w >= 0) fail[w] = 0;
+    }
+    for (uint32_t b = 1; b < S; ++b) {
+        const uint32_t *frow = &delta[size_t(fail[b]) * C];
+        uint32_t *row = &delta[size_t(b) * C];
+        for (uint32_t c = 0; c < C; ++c) {
+            int32_t w = child[size_t(b) * C + c];
+            if (w >= 0) {
+                row[c] = uint32_t(w);
+                fail[w] = frow[c];
+            } else {
+                row[c] = frow[c];
+            }
+        }
+    }
+
+    // ---- output function: own patterns, plus the failure state's outputs
+    std::vector<uint32_t> own_cnt(S + 1, 0);
+    for (auto &e : ends) own_cnt[bfs[e.first] + 1]++;
+    std::vector<uint32_t> own_off(S + 1, 0);
+    for (uint32_t b = 0; b < S; ++b) own_off[b + 1] = own_off[b] + own_cnt[b + 1];
+    std::vector<uint32_t> own_ids(n);
+    {
+        std::vector<uint32_t> fill(own_off.begin(), own_off.end() - 1);
+        for (auto &e : ends) own_ids[fill[bfs[e.first]]++] = e.second;  // ids ascending per state
+    }
+    std::vector<uint32_t> out_off(S + 1, 0);
+    std::vector<uint32_t> out_ids;
+    out_ids.reserve(n);
+    for (uint32_t b = 0; b < S; ++b) {
+        out_off[b] = uint32_t(out_ids.size());
+        const uint32_t *o1 = &own_ids[own_off[b]], *e1 = &own_ids[own_off[b + 1]];
+        uint64_t fo = b ? out_off[fail[b]] : 0, fe = b ? out_off[fail[b] + 1] : 0;
+        if (out_ids.size() + (e1 - o1) + (fe - fo) >= (1ull << 32) - 1) {
+            err = "ac_build: output sets exceed 2^32 entries";
+            return AC_ERR_TOO_LARGE;
+        }
+        // merge two ascending lists; out(fail(b)) was finished earlier
+        size_t base = out_ids.size();
+        out_ids.resize(base + (e1 - o1) + (fe - fo));
+        std::merge(o1, e1, out_ids.begin() + fo, out_ids.begin() + fe, out_ids.begin() + base);
+        out_off[b + 1] = uint32_t(out_ids.size());
+    }
+    // out_off[b+1] of the last written state is also the final sentinel
+    out_off[S] = uint32_t(out_ids.size());
+    auto accepts = [&](uint32_t b) { return out_off[b + 1] > out_off[b]; };
+
+    // ---- final numbering. With an LDS image, the first `hot` ids go to the
+    // shallowest non-final states (breadth-first order approximates visit
+    // frequency on text unrelated to the patterns), then the other targets of
+    // those rows, so every hot-row entry fits 15 bits; then the rest.
+    uint32_t hot_budget = 0;
+    if (plan.lds_bytes > 256) {
+        const bool full_fits = 256ull + uint64_t(S) * C * 4ull <= plan.lds_bytes;
+        if (!(plan.only_if_needed && full_fits)) {
+            hot_budget = (plan.lds_bytes - 256) / (2 * C);
+            if (plan.max_states) hot_budget = std::min(hot_budget, plan.max_states);
+        }
+    }
+    std::vector<uint32_t> perm(S);  // bfs id -> final id
+    uint32_t H = 0;
+    if (hot_budget > 0) {
+        std::vector<uint32_t> cand;
+        for (uint32_t b = 0; b < S && cand.size() < std::min<uint32_t>(hot_budget, kHotIdLimit); ++b)
+            if (!accepts(b)) cand.push_back(b);
+        H = uint32_t(cand.size());
+        std::vector<uint8_t> mark(S);
+        while (H > 0) {
+            std::fill(mark.begin(), mark.end(), 0);
+            for (uint32_t i = 0; i < H; ++i) mark[cand[i]] = 1;
+            uint32_t extra = 0;
+            for (uint32_t i = 0; i < H; ++i)
+                for (uint32_t c = 0; c < C; ++c) {
+                    uint32_t t = delta[size_t(cand[i]) * C + c];
+                    if (!mark[t]) { mark[t] = 2; ++extra; }
+                }
+            if (H + extra <= kHotIdLimit) break;
+            H -= std::max<uint32_t>(1, (H + extra - kHotIdLimit + 1) / 2);
+        }
+        if (H > 0) {
+            uint32_t next = 0;
+            for (uint32_t i = 0; i < H; ++i) perm[cand[i]] = next++;
+            for (uint32_t b = 0; b < S; ++b)
+                if (mark[b] == 2) perm[b] = next++;
+            for (uint32_t b = 0; b < S; ++b)
+                if (!mark[b]) perm[b] = next++;
+        }
+    }
+    if (H == 0)
+        for (uint32_t b = 0; b < S; ++b) perm[b] = b;
+    std::vector<uint32_t> inv(S);
+    for (uint32_t b = 0; b < S; ++b) inv[perm[b]] = b;
+
+    // ---- device tables in final ids
+    m.n_states = S;
+    m.dfa.assign(size_t(S) * C, 0);
+    m.go.assign(size_t(S) * C, 0);
+    m.out_off.assign(S + 1, 0);
+    m.own_off.assign(S + 1, 0);
+    m.out_ids.clear();
+    m.out_ids.reserve(out_ids.size());
+    m.own_ids.clear();
+    m.own_ids.reserve(n);
+    for (uint32_t f = 0; f < S; ++f) {
+        uint32_t b = inv[f];
+        for (uint32_t c = 0; c < C; ++c) {
+            uint32_t t = delta[size_t(b) * C + c];
+            m.dfa[size_t(f) * C + c] = perm[t] | (accepts(t) ? kAccept : 0u);
+            int32_t w = child[size_t(b) * C + c];
+            if (w >= 0)
+                m.go[size_t(f) * C + c] = perm[w] | (own_off[w + 1] > own_off[w] ? kAccept : 0u);
+        }
+        m.out_ids.insert(m.out_ids.end(), out_ids.begin() + out_off[b], out_ids.begin() + out_off[b + 1]);
+        m.out_off[f + 1] = uint32_t(m.out_ids.size());
+        m.own_ids.insert(m.own_ids.end(), own_ids.begin() + own_off[b], own_ids.begin() + own_off[b + 1]);
+        m.own_off[f + 1] = uint32_t(m.own_ids.size());
+    }
+    m.hot_states = H;
+    m.hot_dfa.assign(size_t(H) * C, 0);
+    m.hot_go.assign(size_t(H) * C, 0);
+    for (uint32_t f = 0; f < H; ++f)
+        for (uint32_t c = 0; c < C; ++c) {
+            uint32_t e = m.dfa[size_t(f) * C + c];
+            uint32_t g = m.go[size_t(f) * C + c];
+            // (successors of hot rows were numbered below kHotIdLimit above)
+            m.hot_dfa[size_t(f) * C + c] = uint16_t((e & kStateMask) | ((e & kAccept) ? kHotAccept : 0));
+            m.hot_go[size_t(f) * C + c] = uint16_t((g & kStateMask) | ((g & kAccept) ? kHotAccept : 0));
+        }
+    m.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return AC_OK;
+}
+
+}  // namespace acm

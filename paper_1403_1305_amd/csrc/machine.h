@@ -1,0 +1,72 @@
+// machine.h -- host-side construction of the Aho-Corasick machine (internal).
+//
+// Step 1 of the method (the paper's Sec. II): from the pattern set, build the
+// goto function (a trie), the failure function and the output function
+// (Sec. II.A). The failure transitions are then folded into ordinary ones,
+// so every (state, byte class) pair has exactly one successor: the full-DFA
+// form the paper's Sec. III cites as faster to search than the original.
+// The goto function alone is also kept: it is the failure-less machine of
+// Sec. II.B that the per-start-position (PFAC) matcher walks.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace acm {
+
+// 32-bit table entries: successor state id, top bit set when the successor's
+// output set is non-empty (it is a final state).
+constexpr uint32_t kAccept = 0x80000000u;
+constexpr uint32_t kStateMask = 0x7fffffffu;
+// 16-bit LDS image entries: successor id (< 2^15), top bit as above.
+constexpr uint16_t kHotAccept = 0x8000u;
+constexpr uint16_t kHotMask = 0x7fffu;
+constexpr uint32_t kHotIdLimit = 1u << 15;
+// byte -> column map value for bytes that occur in no pattern
+constexpr uint8_t kNoClass = 0xffu;
+
+struct Machine {
+    uint32_t n_patterns = 0;
+    uint32_t m_max = 0;
+    uint32_t n_states = 0;
+    uint32_t sigma = 0;       // distinct pattern bytes
+    uint32_t n_cols = 0;      // table width
+    uint32_t log2_cols = 0;   // valid when cols_pow2
+    bool cols_pow2 = false;
+    bool hashed = false;      // column = (b >> hash_shift) & (n_cols - 1)
+    uint32_t hash_shift = 0;
+    uint8_t hash_letter[8] = {0};  // the pattern byte owning each hashed column (hashed only)
+    uint8_t cmap[256];        // byte -> column, kNoClass if absent from all patterns
+
+    // Full DFA: dfa[s * n_cols + c] = delta(s, c) | kAccept if it is final.
+    std::vector<uint32_t> dfa;
+    // Output sets in CSR form, ids ascending: out(s) = out_ids[out_off[s] .. out_off[s+1]).
+    std::vector<uint32_t> out_off, out_ids;
+    // Goto function: go[s * n_cols + c] = child | kAccept if the child ends a
+    // pattern itself, or 0 where there is no edge (the root is nobody's child).
+    std::vector<uint32_t> go;
+    // Patterns ending exactly at each state (no failure-chain outputs).
+    std::vector<uint32_t> own_off, own_ids;
+
+    // States [0, hot_states) form the LDS image; every successor of a hot
+    // row is numbered below kHotIdLimit so that it fits 15 bits.
+    uint32_t hot_states = 0;
+    std::vector<uint16_t> hot_dfa;  // hot_states * n_cols, as dfa but 16-bit
+    std::vector<uint16_t> hot_go;   // hot_states * n_cols, as go but 16-bit
+    double build_ms = 0.0;
+};
+
+// What to plan the 16-bit LDS image for.
+struct HotPlan {
+    uint32_t lds_bytes = 0;      // bytes the image may take, 256 of them for the byte map; 0 = none
+    uint32_t max_states = 0;     // cap on its rows, 0 = none
+    bool only_if_needed = true;  // skip it when the whole 32-bit table fits lds_bytes
+};
+
+// Returns 0 or a negative AC_ERR_* code with `err` set. Without an image,
+// states are numbered in plain breadth-first order.
+int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const HotPlan &plan,
+                  Machine &m, std::string &err);
+
+}  // namespace acm

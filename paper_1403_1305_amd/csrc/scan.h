@@ -1,0 +1,52 @@
+// scan.h -- device-side machine image and kernel launchers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace acm {
+
+// Device copy of a Machine (see machine.h); all pointers are device memory
+// owned by the automaton.
+struct DeviceMachine {
+    uint32_t n_states = 0, n_cols = 0, m_max = 0, hot_states = 0;
+    uint32_t log2_cols = 0, hash_shift = 0;
+    bool cols_pow2 = false, hashed = false;
+    uint8_t hash_letter[8] = {0};
+    const uint32_t *dfa = nullptr, *go = nullptr;
+    const uint32_t *out_off = nullptr, *out_ids = nullptr;
+    const uint32_t *own_off = nullptr, *own_ids = nullptr;
+    const uint16_t *hot_dfa = nullptr, *hot_go = nullptr;
+    const uint8_t *cmap = nullptr;  // 256 bytes
+};
+
+struct ScanConfig {
+    uint32_t algo = 0;       // AC_ALGO_*
+    uint32_t chunk = 0;      // DFA chunk bytes (multiple of 16), 0 = auto
+    uint32_t block = 0;      // threads per workgroup, 0 = auto
+    uint32_t placement = 0;  // resolved AC_PLACE_* (never AUTO here)
+};
+
+// LDS bytes a workgroup may use on gfx950.
+constexpr uint32_t kLdsPerWorkgroup = 160u * 1024u;
+
+int compute_units(int device);
+
+// Each returns AC_OK or an AC_ERR_* code with `err` set. Nothing is
+// launched when an error is returned before the first launch.
+int launch_zero_count(uint64_t *d_count, hipStream_t stream, std::string &err);
+int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
+                    uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
+                    std::string &err);
+int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
+                     uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
+                     std::string &err);
+
+// LSD radix sort of uint64 keys (ascending), using d_tmp scratch.
+uint64_t sort_scratch_bytes(uint64_t count);
+int launch_sort(uint64_t *keys, uint64_t count, void *tmp, uint64_t tmp_bytes, hipStream_t stream,
+                std::string &err);
+
+}  // namespace acm

@@ -1,0 +1,200 @@
+"""Host-side tests of libac.so (no GPU): exported symbols, argument checks,
+and the tables ac_build_host produces, walked in Python against the oracle."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from synth import DNA, PROTEIN, plain_workload
+
+ac = pytest.importorskip("paper_1403_1305_amd.ac")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions() -> set[str]:
+    src = open(os.path.join(ROOT, "include", "ac.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"\b(ac_[a-z_]+)\s*\(", src))
+
+
+def test_library_exports_every_declared_function():
+    lib = ac.load_library()
+    declared = header_functions()
+    assert {"ac_build", "ac_scan", "ac_free", "ac_info", "ac_scan_sync", "ac_last_error"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(ac.SIGNATURES), "binding and header disagree"
+
+
+def build_host(patterns, **kw):
+    d, o = ac.patterns_csr(patterns)
+    return ac.ac_build_host(d, o, opts=ac._opts(**kw) if kw else None)
+
+
+def test_invalid_arguments():
+    with pytest.raises(ac.AcError) as e:
+        build_host([b"A", b""])
+    assert e.value.status == ac.AC_ERR_INVALID
+    with pytest.raises(ac.AcError) as e:
+        ac.ac_build_host(np.zeros(1, np.uint8), np.zeros(1, np.uint64))
+    assert e.value.status == ac.AC_ERR_INVALID
+    with pytest.raises(ac.AcError) as e:
+        ac.ac_build_host(np.frombuffer(b"AB", np.uint8), np.array([0, 2, 1], np.uint64))
+    assert e.value.status == ac.AC_ERR_INVALID
+    # a scan on a host-only automaton is rejected before any device work
+    a = build_host([b"AB"])
+    with pytest.raises(ac.AcError) as e:
+        ac.ac_scan(a, 0, 0, 0, 0, 1 << 20)
+    assert e.value.status == ac.AC_ERR_INVALID
+    lib = ac.load_library()
+    assert lib.ac_scan(None, None, 0, None, 0, None, None, None) == ac.AC_ERR_INVALID
+    assert lib.ac_info(None, None) == ac.AC_ERR_INVALID
+    lib.ac_free(None)
+    with pytest.raises(ac.AcError):
+        build_host([b"AB"], placement=ac.AC_PLACE_LDS_FULL, lds_bytes=270)
+
+
+class Tables:
+    def __init__(self, a):
+        self.info = ac.ac_info(a)
+        self.C = self.info["n_cols"]
+        self.S = self.info["n_states"]
+        self.dfa = ac.ac_get_table(a, ac.AC_TABLE_DFA).reshape(self.S, self.C)
+        self.go = ac.ac_get_table(a, ac.AC_TABLE_GO).reshape(self.S, self.C)
+        self.out_off = ac.ac_get_table(a, ac.AC_TABLE_OUT_OFF)
+        self.out_ids = ac.ac_get_table(a, ac.AC_TABLE_OUT_IDS)
+        self.own_off = ac.ac_get_table(a, ac.AC_TABLE_OWN_OFF)
+        self.own_ids = ac.ac_get_table(a, ac.AC_TABLE_OWN_IDS)
+        self.cmap = ac.ac_get_table(a, ac.AC_TABLE_CMAP)
+        H = self.info["hot_states"]
+        self.hot = ac.ac_get_table(a, ac.AC_TABLE_HOT_DFA).reshape(H, self.C)
+        self.hot_go = ac.ac_get_table(a, ac.AC_TABLE_HOT_GO).reshape(H, self.C)
+
+    def dfa_walk(self, text: bytes) -> np.ndarray:
+        s, res = 0, []
+        for i, b in enumerate(text):
+            c = self.cmap[b]
+            e = 0 if c == 255 else int(self.dfa[s, c])
+            s = e & 0x7FFFFFFF
+            if e >> 31:
+                res += [(i << 32) | int(k) for k in self.out_ids[self.out_off[s]:self.out_off[s + 1]]]
+        return np.array(sorted(res), dtype=np.uint64)
+
+    def go_walks(self, text: bytes) -> np.ndarray:
+        res = []
+        for p in range(len(text)):
+            s = 0
+            for j in range(p, len(text)):
+                c = self.cmap[text[j]]
+                if c == 255:
+                    break
+                e = int(self.go[s, c])
+                if e == 0:
+                    break
+                s = e & 0x7FFFFFFF
+                res += [(j << 32) | int(k) for k in self.own_ids[self.own_off[s]:self.own_off[s + 1]]]
+        return np.array(sorted(res), dtype=np.uint64)
+
+
+def check_invariants(t: Tables, patterns):
+    S, C = t.S, t.C
+    assert (t.dfa & 0x7FFFFFFF).max() < S and (t.go & 0x7FFFFFFF).max() < S
+    accept = np.diff(t.out_off.astype(np.int64)) > 0
+    assert np.array_equal((t.dfa >> 31).astype(bool), accept[t.dfa & 0x7FFFFFFF])
+    own = np.diff(t.own_off.astype(np.int64)) > 0
+    nz = t.go != 0
+    assert np.array_equal((t.go[nz] >> 31).astype(bool), own[t.go[nz] & 0x7FFFFFFF])
+    assert not accept[0] and (t.go & 0x7FFFFFFF != 0).sum() == S - 1  # a tree: S-1 edges
+    assert sorted(t.own_ids.tolist()) == list(range(len(patterns)))
+    for s in range(S):  # output sets ascending, own ids inside them
+        o = t.out_ids[t.out_off[s]:t.out_off[s + 1]]
+        assert np.all(np.diff(o.astype(np.int64)) > 0)
+        assert set(t.own_ids[t.own_off[s]:t.own_off[s + 1]]) <= set(o.tolist())
+    alphabet = set(b"".join(patterns))
+    for b in range(256):
+        assert (t.cmap[b] != 255) == (b in alphabet)
+        if b in alphabet:
+            assert t.cmap[b] < C
+    H = t.info["hot_states"]
+    if H:
+        assert (t.hot & 0x7FFF).max() < (1 << 15)
+        assert np.array_equal((t.hot & 0x7FFF).astype(np.uint32), t.dfa[:H] & 0x7FFFFFFF)
+        assert np.array_equal((t.hot >> 15).astype(np.uint32), t.dfa[:H] >> 31)
+        assert np.array_equal((t.hot_go & 0x7FFF).astype(np.uint32), t.go[:H] & 0x7FFFFFFF)
+        assert not accept[:H].any()  # final states are never in the image
+
+
+@pytest.mark.parametrize("placement", [ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_HOT])
+@pytest.mark.parametrize("fixture", [([b"AB", b"ABG", b"BEDE", b"EF"], b"xxABEDEFABG"),
+                                     ([b"HE", b"HIS", b"SHE", b"HERS"], b"USHERSHISHE")])
+def test_worked_examples_tables(fixture, placement):
+    pats, text = fixture
+    t = Tables(build_host(pats, placement=placement))
+    check_invariants(t, pats)
+    expect = oracle.oracle_match(text, pats)
+    assert np.array_equal(t.dfa_walk(text), expect)
+    assert np.array_equal(t.go_walks(text), expect)
+
+
+@st.composite
+def case(draw):
+    alpha = draw(st.sampled_from([b"ab", b"ACGT", b"xyz!", bytes(range(0, 256, 7))]))
+    letter = st.sampled_from(list(alpha))
+    pats = draw(st.lists(st.lists(letter, min_size=1, max_size=9).map(bytes), min_size=1,
+                         max_size=20))
+    text = bytes(draw(st.lists(st.sampled_from(list(alpha) + [0x00, 0x41]), max_size=200)))
+    hot = draw(st.sampled_from([0, 1, 3, 40]))
+    return pats, text, hot
+
+
+@settings(max_examples=400, deadline=None)
+@given(case())
+def test_tables_walk_like_the_oracle(c):
+    pats, text, hot = c
+    kw = dict(placement=ac.AC_PLACE_LDS_HOT, hot_states=hot) if hot else {}
+    t = Tables(build_host(pats, **kw))
+    check_invariants(t, pats)
+    expect = oracle.oracle_match(text, pats)
+    assert np.array_equal(t.dfa_walk(text), expect)
+    assert np.array_equal(t.go_walks(text), expect)
+
+
+def test_dna_classes_are_hashed():
+    t = Tables(build_host([b"ACGT", b"TTGA"]))
+    assert t.info["class_hashed"] == 1 and t.C == 4 and t.info["class_shift"] == 1
+    assert [t.cmap[b] for b in b"ACGT"] == [0, 1, 3, 2]
+
+
+def test_protein_classes_are_ranked():
+    t = Tables(build_host([PROTEIN]))
+    assert t.info["class_hashed"] == 0 and t.C == 20 and t.info["sigma"] == 20
+    assert [t.cmap[b] for b in sorted(PROTEIN)] == list(range(20))
+
+
+def test_small_workload_tables():
+    w = plain_workload("dna1m", n=1 << 14)
+    a = build_host(w.patterns)
+    t = Tables(a)
+    check_invariants(t, w.patterns)
+    assert t.info["placement"] == ac.AC_PLACE_LDS_FULL  # ~900 states x 4 columns fits LDS
+    text = w.text[:3000].tobytes()
+    assert np.array_equal(t.dfa_walk(text), oracle.oracle_match(text, w.patterns))
+    assert t.info["n_states"] == oracle.OracleAC(w.patterns).n_states
+
+
+def test_hot_image_for_large_dna_set():
+    """A 10,000-pattern DNA set does not fit LDS as a 32-bit table: the build
+    plans a 16-bit image of the shallowest non-final states."""
+    w = plain_workload("dna256m", n=1 << 16)
+    t = Tables(build_host(w.patterns))
+    assert t.info["placement"] == ac.AC_PLACE_LDS_HOT
+    assert 10_000 < t.info["hot_states"] <= ((160 - 2) * 1024 - 256) // 8
+    check_invariants(t, w.patterns)
+    text = w.text[:2000].tobytes()
+    assert np.array_equal(t.dfa_walk(text), oracle.oracle_match(text, w.patterns))
