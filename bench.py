@@ -71,9 +71,13 @@ def main():
     p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC))
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
-    p.add_argument("--cpu-sample-mib", type=int, default=128)
+    p.add_argument("--cpu-sample-mib", type=int, default=256)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-pfac", action="store_true")
+    p.add_argument("--walkers", type=int, default=0)
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run one plain device copy of the text's size (the reference "
+                        "kernel for scaling FETCH_SIZE / WRITE_SIZE counter readings)")
     args = p.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -104,7 +108,7 @@ def main():
     cap = 1 << 24
     outs = torch.empty(cap, dtype=torch.int64, device="cuda")
     count = torch.zeros(1, dtype=torch.int64, device="cuda")
-    opts = ac._scan_opts(ac.AC_ALGO_DFA, args.chunk, 0, args.placement)
+    opts = ac._scan_opts(ac.AC_ALGO_DFA, args.chunk, 0, args.placement, args.walkers)
 
     def step(i):
         t = copies[i % 3]
@@ -140,6 +144,11 @@ def main():
         pwall, pms = time_steps(pstep, max(3, args.steps // 4), stream, torch)
         pfac = {"value": round(n * len(pms) / pwall / 1e9, 3), "unit": "GB/s",
                 "kernel_ms": round(float(np.mean(pms)), 4), "matches": int(count.item())}
+
+    if args.calib_copy:
+        dst = torch.empty_like(copies[0])
+        dst.copy_(copies[1])
+        torch.cuda.synchronize()
 
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_sample_mib << 20)
 

@@ -61,7 +61,8 @@ typedef struct ac_automaton ac_automaton;
 typedef struct {
     uint32_t placement;   /* AC_PLACE_*; default AC_PLACE_AUTO */
     uint32_t hot_states;  /* cap on states in the LDS_HOT image; 0 = as many as fit */
-    uint32_t lds_bytes;   /* LDS budget for the table image; 0 = 160 KiB less 2 KiB */
+    uint32_t lds_bytes;   /* LDS budget for the table image; 0 = 151 KiB (the rest of
+                             the 160 KiB holds per-wave match queues) */
     uint32_t reserved;
 } ac_build_opts;
 
@@ -117,8 +118,8 @@ enum {
     AC_TABLE_OUT_IDS = 3, /* uint32: pattern ids, ascending within each set */
     AC_TABLE_OWN_OFF = 4, /* uint32 [n_states+1]: patterns ending exactly at s */
     AC_TABLE_OWN_IDS = 5, /* uint32 */
-    AC_TABLE_HOT_DFA = 6, /* uint16 [hot_states][n_cols]: DFA rows of the LDS image,
-                             successor | 1<<15 if final */
+    AC_TABLE_HOT_DFA = 6, /* uint16 [hot_states][n_cols] (plus one zero if the count is
+                             odd): DFA rows of the LDS image, successor | 1<<15 if final */
     AC_TABLE_HOT_GO = 7,  /* uint16 [hot_states][n_cols]: goto rows of the LDS image */
     AC_TABLE_CMAP = 8     /* uint8 [256]: byte -> column, 255 = byte in no pattern */
 };
@@ -143,8 +144,11 @@ typedef struct {
     uint32_t algo;      /* AC_ALGO_DFA (default) or AC_ALGO_PFAC */
     uint32_t chunk;     /* DFA: text bytes owned by one walker; multiple of 16;
                            0 = chosen from the text length */
-    uint32_t block;     /* threads per workgroup, multiple of 64, <= 1024; 0 = auto */
+    uint32_t block;     /* threads per workgroup; 0 = the placement's own (the only
+                           value accepted otherwise) */
     uint32_t placement; /* 0 = the automaton's; else an AC_PLACE_* override */
+    uint32_t walkers;   /* DFA: chunks walked in lockstep by each lane (1, 2 or 4);
+                           0 = auto */
 } ac_scan_opts;
 
 /*

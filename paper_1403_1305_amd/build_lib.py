@@ -23,7 +23,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function", f"-I{ROOT}/include"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", f"-I{ROOT}/include"]
 
-HIP_SOURCES = ["scan.hip", "api.hip"]
+HIP_SOURCES = ["dfa.hip", "scan.hip", "api.hip"]
 CXX_SOURCES = ["machine.cpp"]
 
 

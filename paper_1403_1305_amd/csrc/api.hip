@@ -6,6 +6,7 @@
 #include <string>
 
 #include "../../include/ac.h"
+#include "device_common.h"
 #include "machine.h"
 #include "scan.h"
 
@@ -27,9 +28,10 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
-// Largest LDS image, in bytes, a build may plan for.
+// Largest LDS image, in bytes, a build may plan for: the LDS of a workgroup
+// less the match queues of 16 waves and some slack.
 uint32_t lds_budget(const ac_build_opts *o) {
-    const uint32_t dflt = acm::kLdsPerWorkgroup - 2048;
+    const uint32_t dflt = acm::kLdsPerWorkgroup - 9 * 1024;
     if (!o || o->lds_bytes == 0) return dflt;
     return std::min(o->lds_bytes, dflt);
 }
@@ -99,8 +101,10 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
 bool resolve_placement(const ac_automaton *a, uint32_t want, uint32_t &place) {
     place = want == AC_PLACE_AUTO ? a->placement : want;
     if (place == AC_PLACE_LDS_HOT && a->m.hot_states == 0) return false;
+    // the whole-table kernels run 256 threads: 4 waves of match queues beside the table
     if (place == AC_PLACE_LDS_FULL &&
-        256ull + uint64_t(a->m.n_states) * a->m.n_cols * 4ull > acm::kLdsPerWorkgroup)
+        256ull + uint64_t(a->m.n_states) * a->m.n_cols * 4ull + 4ull * acm::kQueueBytesPerWave >
+            acm::kLdsPerWorkgroup)
         return false;
     return place <= AC_PLACE_LDS_HOT;
 }
@@ -231,6 +235,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         cfg.algo = opts->algo;
         cfg.chunk = opts->chunk;
         cfg.block = opts->block;
+        cfg.walkers = opts->walkers;
         want = opts->placement;
     }
     if (cfg.algo > AC_ALGO_PFAC) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");

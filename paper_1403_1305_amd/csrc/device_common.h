@@ -1,0 +1,120 @@
+// device_common.h -- match compaction and launch helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ac.h"
+
+namespace acm {
+
+// Rank of this lane among the set lanes of `mask` below it (mbcnt prefix).
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+// Per-wave match staging. Each wave owns kQueueKeys key slots and one count
+// word of LDS; matches are appended with a ballot and an mbcnt rank, and a
+// full queue is flushed to the global list with one atomic on the global
+// counter and coalesced writes. Only the owning wave touches its slots, so no
+// barrier is involved. The count lives in LDS (not in a register) because
+// callers may run with only some lanes active.
+constexpr uint32_t kQueueKeys = 64;
+constexpr uint32_t kQueueBytesPerWave = kQueueKeys * 8 + 16;
+
+struct Emitter {
+    uint64_t *q;   // this wave's LDS key slots
+    uint32_t *qn;  // this wave's LDS count word
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+
+    // Point at the wave's region of `lds` (kQueueBytesPerWave per wave) and
+    // clear its count. Call once per wave before any emit.
+    __device__ __forceinline__ void init(uint8_t *lds, uint64_t *out_, uint64_t cap_,
+                                         unsigned long long *count_) {
+        const uint32_t wave = threadIdx.x / 64;
+        q = reinterpret_cast<uint64_t *>(lds + wave * kQueueBytesPerWave);
+        qn = reinterpret_cast<uint32_t *>(lds + wave * kQueueBytesPerWave + kQueueKeys * 8);
+        out = out_;
+        cap = cap_;
+        count = count_;
+        if (__lane_id() == 0) *qn = 0;
+    }
+
+    // Copy the n staged keys out with the active lanes.
+    __device__ __forceinline__ void drain(uint32_t n) {
+        const uint64_t act = __ballot(true);
+        const uint32_t r = lane_rank(act), w = uint32_t(__popcll(act));
+        unsigned long long base = 0;
+        if (r == 0) base = atomicAdd(count, (unsigned long long)n);
+        base = __shfl(base, __ffsll((unsigned long long)act) - 1);
+        for (uint32_t i = r; i < n; i += w) {
+            const uint64_t idx = base + i;
+            if (idx < cap) out[idx] = q[i];
+        }
+    }
+
+    // Append `key` for every active lane with `has`.
+    __device__ __forceinline__ void emit(bool has, uint64_t key) {
+        const uint64_t mask = __ballot(has);
+        if (mask == 0) return;
+        const uint32_t c = uint32_t(__popcll(mask));
+        uint32_t n = *qn;
+        if (n + c > kQueueKeys) {
+            drain(n);
+            n = 0;
+        }
+        if (has) q[n + lane_rank(mask)] = key;
+        if (lane_rank(__ballot(true)) == 0) *qn = n + c;
+    }
+
+    // Flush what is staged (at the end of the kernel).
+    __device__ __forceinline__ void flush() {
+        const uint32_t n = *qn;
+        if (n) drain(n);
+        if (lane_rank(__ballot(true)) == 0) *qn = 0;
+    }
+};
+
+// Every pattern id of the set ids[off[s] .. off[s+1]) as a match ending at pos.
+__device__ __forceinline__ void emit_set(Emitter &em, bool has, uint32_t s, uint64_t pos,
+                                         const uint32_t *off, const uint32_t *ids) {
+    uint32_t k = 0, kend = 0;
+    if (has) {
+        k = off[s];
+        kend = off[s + 1];
+    }
+    while (__any(k < kend)) {
+        const bool h = k < kend;
+        const uint32_t id = h ? ids[k] : 0u;
+        em.emit(h, (pos << 32) | id);
+        k += h ? 1u : 0u;
+    }
+}
+
+inline int hip_fail(hipError_t e, const char *what, std::string &err) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return AC_ERR_HIP;
+}
+
+// Launch with `lds` bytes of dynamic LDS (raising the per-kernel limit when
+// above 64 KiB) and report launch errors.
+template <typename K, typename A>
+int launch_kernel(K kernel, uint32_t grid, uint32_t block, uint32_t lds, hipStream_t stream,
+                  const A &args, std::string &err) {
+    if (lds > 64u * 1024u) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute", err);
+    }
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, args);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch", err);
+    return AC_OK;
+}
+
+}  // namespace acm

@@ -286,6 +286,9 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
             m.hot_dfa[size_t(f) * C + c] = uint16_t((e & kStateMask) | ((e & kAccept) ? kHotAccept : 0));
             m.hot_go[size_t(f) * C + c] = uint16_t((g & kStateMask) | ((g & kAccept) ? kHotAccept : 0));
         }
+    // 16-bit images are copied as 32-bit words: pad them to whole words
+    if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);
+    if (m.hot_go.size() & 1) m.hot_go.push_back(0);
     m.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return AC_OK;
 }

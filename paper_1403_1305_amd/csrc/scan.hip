@@ -1,6 +1,6 @@
-// scan.hip -- gfx950 kernels: chunked full-DFA scan, failure-less (PFAC)
-// per-start scan, wave-level match compaction, and an LSD radix sort of the
-// match keys.
+// scan.hip -- gfx950 kernels: failure-less (PFAC) per-start scan, the match
+// counter reset, and an LSD radix sort of the match keys. The chunked DFA
+// scan is in dfa.hip.
 #include "scan.h"
 
 #include <algorithm>
@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/ac.h"
+#include "device_common.h"
 #include "machine.h"
 
 namespace acm {
@@ -15,160 +16,7 @@ namespace {
 
 constexpr uint32_t kNoClassDev = 0xffu;
 
-// ------------------------------------------------------------------ compaction
-// Rank of this lane among the set lanes of `mask` below it (mbcnt prefix).
-__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-}
-
-// Append `key` for every active lane with `has`: one ballot, one atomic per
-// wave, each lane writing at base + its rank. Keys past `cap` are counted but
-// not stored.
-__device__ __forceinline__ void emit_key(bool has, uint64_t key, uint64_t *out, uint64_t cap,
-                                         unsigned long long *count) {
-    const uint64_t mask = __ballot(has);
-    if (mask == 0) return;
-    const uint32_t rank = lane_rank(mask);
-    unsigned long long base = 0;
-    if (has && rank == 0) base = atomicAdd(count, (unsigned long long)__popcll(mask));
-    base = __shfl(base, __ffsll((unsigned long long)mask) - 1);
-    if (has) {
-        const uint64_t idx = base + rank;
-        if (idx < cap) out[idx] = key;
-    }
-}
-
-// Every pattern id of the set ids[off[s] .. off[s+1]) as a match ending at pos.
-__device__ __forceinline__ void emit_set(bool has, uint32_t s, uint64_t pos, const uint32_t *off,
-                                         const uint32_t *ids, uint64_t *out, uint64_t cap,
-                                         unsigned long long *count) {
-    uint32_t k = 0, kend = 0;
-    if (has) {
-        k = off[s];
-        kend = off[s + 1];
-    }
-    while (__any(k < kend)) {
-        const bool h = k < kend;
-        const uint32_t id = h ? ids[k] : 0u;
-        emit_key(h, (pos << 32) | id, out, cap, count);
-        k += h ? 1u : 0u;
-    }
-}
-
 __global__ void zero_count_kernel(unsigned long long *count) { *count = 0ull; }
-
-// ------------------------------------------------------------------ DFA scan
-struct DfaArgs {
-    const uint8_t *text;
-    uint64_t n;
-    uint64_t n_chunks;
-    uint32_t chunk;
-    uint32_t m_max;
-    uint32_t n_cols;
-    uint32_t hot_states;
-    uint32_t table_words;  // LDS_FULL: n_states * n_cols
-    const uint32_t *dfa;
-    const uint16_t *hot;
-    const uint8_t *cmap;
-    const uint32_t *out_off, *out_ids;
-    uint64_t *out;
-    uint64_t cap;
-    unsigned long long *count;
-};
-
-template <int PLACE>
-__device__ __forceinline__ uint32_t dfa_entry(uint32_t s, uint32_t c, const DfaArgs &a,
-                                              const uint32_t *s_tab, const uint16_t *s_hot) {
-    const uint32_t idx = s * a.n_cols + c;
-    if constexpr (PLACE == AC_PLACE_LDS_FULL) {
-        return s_tab[idx];
-    } else if constexpr (PLACE == AC_PLACE_LDS_HOT) {
-        if (s < a.hot_states) {
-            const uint32_t e = s_hot[idx];
-            return (e & kHotMask) | ((e & kHotAccept) << 16);
-        }
-        return a.dfa[idx];
-    } else {
-        return a.dfa[idx];
-    }
-}
-
-// One byte through the DFA: bytes outside the pattern alphabet send the
-// walk back to the root; the table is still read (at column 0) so the
-// lookup never leaves the table.
-template <int PLACE>
-__device__ __forceinline__ uint32_t dfa_byte(uint32_t s, uint32_t b, const DfaArgs &a,
-                                             const uint8_t *s_cmap, const uint32_t *s_tab,
-                                             const uint16_t *s_hot) {
-    const uint32_t c = s_cmap[b];
-    const bool valid = c != kNoClassDev;
-    const uint32_t e = dfa_entry<PLACE>(s, valid ? c : 0u, a, s_tab, s_hot);
-    return valid ? e : 0u;
-}
-
-// Chunk k owns end positions [kC, min(kC + C, n)). Its walker starts from the
-// root at max(0, kC - m_max + 1) rounded down to 16 bytes: every occurrence
-// ending in the chunk starts at or after kC - m_max + 1, and a walk from the
-// root reports every occurrence starting at or after its first byte, so the
-// walker sees exactly the occurrences it owns (plus some it discards).
-template <int PLACE, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) dfa_scan_kernel(DfaArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint8_t *s_cmap = smem;
-    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + 256);
-    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + 256);
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < 64; i += BLOCK)
-        reinterpret_cast<uint32_t *>(s_cmap)[i] = reinterpret_cast<const uint32_t *>(a.cmap)[i];
-    if constexpr (PLACE == AC_PLACE_LDS_FULL) {
-        for (uint32_t i = tid; i < a.table_words; i += BLOCK) s_tab[i] = a.dfa[i];
-    } else if constexpr (PLACE == AC_PLACE_LDS_HOT) {
-        const uint32_t halfwords = a.hot_states * a.n_cols;
-        for (uint32_t i = tid; i < halfwords; i += BLOCK) s_hot[i] = a.hot[i];
-    }
-    __syncthreads();
-
-    const uint64_t stride = uint64_t(gridDim.x) * BLOCK;
-    for (uint64_t k = uint64_t(blockIdx.x) * BLOCK + tid; k < a.n_chunks; k += stride) {
-        const uint64_t own_lo = k * a.chunk;
-        const uint64_t own_hi = min(own_lo + a.chunk, a.n);
-        const uint64_t back = a.m_max - 1;
-        uint64_t pos = own_lo > back ? ((own_lo - back) & ~uint64_t(15)) : 0;
-        const uint64_t full_end = own_hi & ~uint64_t(15);
-        uint32_t s = 0;
-        for (; pos < full_end; pos += 16) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(a.text + pos);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-            const uint32_t s0 = s;
-            uint32_t flag = 0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t e = dfa_byte<PLACE>(s, (w[j >> 2] >> ((j & 3) * 8)) & 0xffu, a,
-                                                   s_cmap, s_tab, s_hot);
-                s = e & kStateMask;
-                flag |= e;
-            }
-            if (flag & kAccept) {
-                // some state in these 16 bytes is final: walk them again and report
-                uint32_t r = s0;
-                for (int j = 0; j < 16; ++j) {
-                    const uint32_t e = dfa_byte<PLACE>(r, (w[j >> 2] >> ((j & 3) * 8)) & 0xffu, a,
-                                                       s_cmap, s_tab, s_hot);
-                    r = e & kStateMask;
-                    const bool acc = (e & kAccept) && (pos + j >= own_lo);
-                    emit_set(acc, r, pos + j, a.out_off, a.out_ids, a.out, a.cap, a.count);
-                }
-            }
-        }
-        for (; pos < own_hi; ++pos) {  // last bytes of a text whose length is not a multiple of 16
-            const uint32_t e = dfa_byte<PLACE>(s, a.text[pos], a, s_cmap, s_tab, s_hot);
-            s = e & kStateMask;
-            emit_set((e & kAccept) && pos >= own_lo, s, pos, a.out_off, a.out_ids, a.out, a.cap,
-                     a.count);
-        }
-    }
-}
 
 // ------------------------------------------------------------------ PFAC scan
 struct PfacArgs {
@@ -212,14 +60,18 @@ __device__ __forceinline__ uint32_t go_entry(uint32_t s, uint32_t c, const PfacA
 // exactly at each state entered, until a byte has no edge.
 template <int PLACE, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) pfac_scan_kernel(PfacArgs a) {
+    // LDS: per-wave match queues | byte map | staged text classes | table image
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr uint32_t kTile = BLOCK * kPfacStartsPerThread;
-    uint8_t *s_cmap = smem;
-    uint8_t *s_cls = smem + 256;  // kTile + halo classes, padded to 16
+    constexpr uint32_t kQueues = (BLOCK / 64) * kQueueBytesPerWave;
+    uint8_t *s_cmap = smem + kQueues;
+    uint8_t *s_cls = smem + kQueues + 256;  // kTile + halo classes, padded to 16
     const uint32_t cls_bytes = (kTile + a.halo + 15u) & ~15u;
-    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + 256 + cls_bytes);
-    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + 256 + cls_bytes);
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + kQueues + 256 + cls_bytes);
+    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + kQueues + 256 + cls_bytes);
     const uint32_t tid = threadIdx.x;
+    Emitter em;
+    em.init(smem, a.out, a.cap, a.count);
     for (uint32_t i = tid; i < 64; i += BLOCK)
         reinterpret_cast<uint32_t *>(s_cmap)[i] = reinterpret_cast<const uint32_t *>(a.cmap)[i];
     if constexpr (PLACE == AC_PLACE_LDS_FULL) {
@@ -246,11 +98,12 @@ __global__ void __launch_bounds__(BLOCK) pfac_scan_kernel(PfacArgs a) {
                 if (e == 0) break;
                 s = e & kStateMask;
                 if (__any(e & kAccept))
-                    emit_set((e & kAccept) != 0, s, j, a.own_off, a.own_ids, a.out, a.cap, a.count);
+                    emit_set(em, (e & kAccept) != 0, s, j, a.own_off, a.own_ids);
             }
         }
         __syncthreads();
     }
+    em.flush();
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -339,26 +192,6 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const uint64_t
     }
 }
 
-// ------------------------------------------------------------------ helpers
-int hip_fail(hipError_t e, const char *what, std::string &err) {
-    err = std::string(what) + ": " + hipGetErrorString(e);
-    return AC_ERR_HIP;
-}
-
-template <typename K, typename A>
-int launch(K kernel, uint32_t grid, uint32_t block, uint32_t lds, hipStream_t stream, const A &args,
-           std::string &err) {
-    if (lds > 64u * 1024u) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute", err);
-    }
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, args);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "kernel launch", err);
-    return AC_OK;
-}
-
 }  // namespace
 
 int compute_units(int device) {
@@ -382,74 +215,6 @@ int launch_zero_count(uint64_t *d_count, hipStream_t stream, std::string &err) {
                        reinterpret_cast<unsigned long long *>(d_count));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AC_OK : hip_fail(e, "zero_count launch", err);
-}
-
-int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                    uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
-                    std::string &err) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    const uint32_t cus = uint32_t(compute_units(dev));
-    DfaArgs a{};
-    a.text = text;
-    a.n = n;
-    a.m_max = dm.m_max;
-    a.n_cols = dm.n_cols;
-    a.hot_states = dm.hot_states;
-    a.table_words = dm.n_states * dm.n_cols;
-    a.dfa = dm.dfa;
-    a.hot = dm.hot_dfa;
-    a.cmap = dm.cmap;
-    a.out_off = dm.out_off;
-    a.out_ids = dm.out_ids;
-    a.out = out;
-    a.cap = cap;
-    a.count = reinterpret_cast<unsigned long long *>(count);
-
-    uint32_t lds = 256;
-    if (cfg.placement == AC_PLACE_LDS_FULL) lds += a.table_words * 4u;
-    if (cfg.placement == AC_PLACE_LDS_HOT) lds += ((dm.hot_states * dm.n_cols * 2u) + 15u) & ~15u;
-    if (lds > kLdsPerWorkgroup) {
-        err = "ac_scan: table image does not fit the LDS";
-        return AC_ERR_INVALID;
-    }
-    const uint32_t block = cfg.placement == AC_PLACE_LDS_HOT ? 1024u : 256u;
-    if (cfg.block != 0 && cfg.block != block) {
-        err = "ac_scan: this placement runs with " + std::to_string(block) + " threads per workgroup";
-        return AC_ERR_INVALID;
-    }
-    const uint32_t wg_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(2048 / block, kLdsPerWorkgroup / lds));
-    // Chunk length: enough walkers to fill every lane the chip can hold, but at
-    // least 4 * m_max so the overlap stays small.
-    uint64_t chunk = cfg.chunk;
-    if (chunk == 0) {
-        const uint64_t walkers = uint64_t(cus) * wg_per_cu * block;
-        chunk = (n + walkers - 1) / walkers;
-        chunk = std::max<uint64_t>(chunk, 4ull * dm.m_max);
-        chunk = std::max<uint64_t>(64, (chunk + 15) & ~uint64_t(15));
-        chunk = std::min<uint64_t>(chunk, 1u << 30);
-    }
-    if (chunk % 16 != 0 || chunk == 0) {
-        err = "ac_scan: chunk must be a positive multiple of 16";
-        return AC_ERR_INVALID;
-    }
-    a.chunk = uint32_t(chunk);
-    a.n_chunks = (n + chunk - 1) / chunk;
-    if (a.n_chunks == 0) return AC_OK;
-    const uint64_t want = (a.n_chunks + block - 1) / block;
-    uint64_t cap_grid = want;
-    if (cfg.placement != AC_PLACE_GLOBAL) cap_grid = uint64_t(cus) * wg_per_cu;
-    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(want, cap_grid)));
-    switch (cfg.placement) {
-        case AC_PLACE_GLOBAL:
-            return launch(dfa_scan_kernel<AC_PLACE_GLOBAL, 256>, grid, block, lds, stream, a, err);
-        case AC_PLACE_LDS_FULL:
-            return launch(dfa_scan_kernel<AC_PLACE_LDS_FULL, 256>, grid, block, lds, stream, a, err);
-        case AC_PLACE_LDS_HOT:
-            return launch(dfa_scan_kernel<AC_PLACE_LDS_HOT, 1024>, grid, block, lds, stream, a, err);
-    }
-    err = "ac_scan: unknown placement";
-    return AC_ERR_INVALID;
 }
 
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
@@ -481,7 +246,7 @@ int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long *>(count);
     const uint32_t tile = block * kPfacStartsPerThread;
-    uint32_t lds = 256 + ((tile + a.halo + 15u) & ~15u);
+    uint32_t lds = (block / 64) * kQueueBytesPerWave + 256 + ((tile + a.halo + 15u) & ~15u);
     uint32_t place = cfg.placement;
     // the staged text shares the LDS with the table: a whole table that no
     // longer fits beside it is read from global memory instead
@@ -506,11 +271,11 @@ int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(g, 1u << 30)));
     switch (place) {
         case AC_PLACE_GLOBAL:
-            return launch(pfac_scan_kernel<AC_PLACE_GLOBAL, block>, grid, block, lds, stream, a, err);
+            return launch_kernel(pfac_scan_kernel<AC_PLACE_GLOBAL, block>, grid, block, lds, stream, a, err);
         case AC_PLACE_LDS_FULL:
-            return launch(pfac_scan_kernel<AC_PLACE_LDS_FULL, block>, grid, block, lds, stream, a, err);
+            return launch_kernel(pfac_scan_kernel<AC_PLACE_LDS_FULL, block>, grid, block, lds, stream, a, err);
         case AC_PLACE_LDS_HOT:
-            return launch(pfac_scan_kernel<AC_PLACE_LDS_HOT, block>, grid, block, lds, stream, a, err);
+            return launch_kernel(pfac_scan_kernel<AC_PLACE_LDS_HOT, block>, grid, block, lds, stream, a, err);
     }
     err = "ac_scan: unknown placement";
     return AC_ERR_INVALID;

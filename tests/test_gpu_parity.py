@@ -49,16 +49,18 @@ def to_device(text) -> "torch.Tensor":
     return t[: len(a)]
 
 
-def gpu_keys(auto, text, algo=ac.AC_ALGO_DFA, chunk=0, placement=0, capacity=None) -> np.ndarray:
+def gpu_keys(auto, text, algo=ac.AC_ALGO_DFA, chunk=0, placement=0, capacity=None,
+             walkers=0) -> np.ndarray:
     d = to_device(text) if not isinstance(text, torch.Tensor) else text
-    keys = ac.scan_text(auto, d, capacity=capacity, opts=ac._scan_opts(algo, chunk, 0, placement))
+    keys = ac.scan_text(auto, d, capacity=capacity,
+                        opts=ac._scan_opts(algo, chunk, 0, placement, walkers))
     return np.sort(ac.keys_to_numpy(keys))
 
 
 def placements_for(auto):
     info = ac.ac_info(auto)
     out = [ac.AC_PLACE_GLOBAL]
-    if 256 + info["table_bytes"] <= 160 * 1024:
+    if 256 + info["table_bytes"] + 4 * 528 <= 160 * 1024:
         out.append(ac.AC_PLACE_LDS_FULL)
     if info["hot_states"]:
         out.append(ac.AC_PLACE_LDS_HOT)
@@ -102,11 +104,12 @@ def test_small_dna(small, algo, placement):
     assert got.size == expect.size and np.array_equal(got, expect)
 
 
+@pytest.mark.parametrize("walkers", [1, 2, 4])
 @pytest.mark.parametrize("chunk", [16, 32, 48, 64, 80, 1024, 4096, 1 << 20])
-def test_small_dna_chunk_lengths(small, chunk):
+def test_small_dna_chunk_lengths(small, chunk, walkers):
     w, expect = small
     a = build(w.patterns)
-    assert np.array_equal(gpu_keys(a, w.text, chunk=chunk), expect)
+    assert np.array_equal(gpu_keys(a, w.text, chunk=chunk, walkers=walkers), expect)
 
 
 def test_determinism(small):
@@ -140,9 +143,11 @@ def boundary_case(chunk: int, m: int, n: int, seed: int):
 def test_chunk_boundaries(chunk, m):
     text, pats = boundary_case(chunk, m, 6 * chunk + 37, seed=chunk * 100 + m)
     expect = oracle.oracle_match(text, pats)
-    for placement in (ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL):
-        a = build(pats, placement=placement)
-        assert np.array_equal(gpu_keys(a, text, chunk=chunk), expect), (chunk, m, placement)
+    for placement in (ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_HOT):
+        a = build(pats, placement=placement, hot_states=7 if placement == ac.AC_PLACE_LDS_HOT else 0)
+        for walkers in ((1, 2) if placement == ac.AC_PLACE_LDS_HOT else (1, 2, 4)):
+            assert np.array_equal(gpu_keys(a, text, chunk=chunk, walkers=walkers), expect), \
+                (chunk, m, placement, walkers)
     a = build(pats)
     assert np.array_equal(gpu_keys(a, text, algo=ac.AC_ALGO_PFAC), expect)
 
@@ -156,10 +161,12 @@ def test_ragged_and_tiny_texts(n):
         a = build(pats, placement=placement)
         for algo in (ac.AC_ALGO_DFA, ac.AC_ALGO_PFAC):
             for chunk in (0, 16, 32):
-                if algo == ac.AC_ALGO_PFAC and chunk:
-                    continue
-                assert np.array_equal(gpu_keys(a, text, algo=algo, chunk=chunk), expect), \
-                    (n, placement, algo, chunk)
+                for walkers in (((1, 2) if placement == ac.AC_PLACE_LDS_HOT else (1, 2, 4))
+                                if algo == ac.AC_ALGO_DFA else (0,)):
+                    if algo == ac.AC_ALGO_PFAC and chunk:
+                        continue
+                    assert np.array_equal(gpu_keys(a, text, algo=algo, chunk=chunk, walkers=walkers),
+                                          expect), (n, placement, algo, chunk, walkers)
 
 
 def test_bytes_outside_the_alphabet():
