@@ -149,6 +149,8 @@ typedef struct {
     uint32_t placement; /* 0 = the automaton's; else an AC_PLACE_* override */
     uint32_t walkers;   /* DFA: chunks walked in lockstep by each lane (1, 2 or 4);
                            0 = auto */
+    uint32_t block_bytes; /* DFA: text bytes a walker loads at once (64 or 128);
+                             0 = auto */
 } ac_scan_opts;
 
 /*

@@ -63,7 +63,7 @@ class ac_info_t(ctypes.Structure):
 class ac_scan_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("block", ctypes.c_uint32), ("placement", ctypes.c_uint32),
-                ("walkers", ctypes.c_uint32)]
+                ("walkers", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -207,8 +207,8 @@ def ac_get_table(a: Automaton, which: int) -> np.ndarray:
     return out[: size.value // np.dtype(dt).itemsize]
 
 
-def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0, walkers=0):
-    return ac_scan_opts(algo, chunk, block, placement, walkers)
+def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0, walkers=0, block_bytes=0):
+    return ac_scan_opts(algo, chunk, block, placement, walkers, block_bytes)
 
 
 def ac_scan(a: Automaton, d_text, n: int, d_matches, capacity: int, d_count,

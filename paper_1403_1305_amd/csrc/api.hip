@@ -134,6 +134,8 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
     dm.n_cols = m.n_cols;
     dm.m_max = m.m_max;
     dm.hot_states = m.hot_states;
+    dm.term_end = m.term_end;
+    dm.acc_end = m.acc_end;
     dm.log2_cols = m.log2_cols;
     dm.cols_pow2 = m.cols_pow2;
     dm.hashed = m.hashed;
@@ -236,6 +238,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         cfg.chunk = opts->chunk;
         cfg.block = opts->block;
         cfg.walkers = opts->walkers;
+        cfg.block_bytes = opts->block_bytes;
         want = opts->placement;
     }
     if (cfg.algo > AC_ALGO_PFAC) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");

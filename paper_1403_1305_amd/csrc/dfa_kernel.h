@@ -1,0 +1,412 @@
+// dfa_kernel.h -- the chunked full-DFA scan kernel for gfx950 (templates;
+// instantiated per table placement in dfa_place_*.hip, launched from dfa.hip).
+//
+// The text is cut into chunks of C bytes. Chunk k owns the end positions
+// [kC, min(kC + C, n)); its walker starts from the root exactly m_max - 1
+// bytes before kC (or at 0) and reports only the matches that end inside the
+// chunk. Every occurrence ending in the chunk starts at or after
+// kC - m_max + 1, and a walk from the root reports every occurrence that
+// starts at or after its first byte, so each match is reported exactly once.
+//
+// Each lane runs K walkers on K different chunks in lockstep, so K table
+// lookups are in flight per lane per step. Text arrives in 16-byte groups
+// that are prefetched two groups ahead. A walker only ORs the final-state
+// flags of a group together; a flagged group is walked again and reported
+// (final states are rare next to plain steps).
+//
+// Table placements:
+//   LDS_FULL  the whole 32-bit table in LDS.
+//   LDS_HOT   16-bit rows of the hot states [0, H) in LDS; a state >= H is
+//             looked up in the 32-bit table in global memory (L2 resident).
+//   GLOBAL    every lookup from the 32-bit table in global memory.
+// Byte classes are either a bit field of the byte (small alphabets, checked
+// four bytes at a time with v_perm against the letter of each field value) or
+// a 256-entry map in LDS.
+#pragma once
+
+#include <algorithm>
+
+#include "../../include/ac.h"
+#include "device_common.h"
+#include "machine.h"
+#include "scan.h"
+
+namespace acm {
+namespace dfa {
+
+constexpr uint32_t kNoClassDev = 0xffu;
+
+struct DfaArgs {
+    const uint8_t *text;
+    uint32_t n;            // text bytes (< 2^32)
+    uint32_t chunk;        // bytes owned per walker (multiple of 16)
+    uint32_t n_chunks;
+    uint32_t back;         // m_max - 1
+    uint32_t n_cols;
+    uint32_t hot;          // H: states with rows in the LDS image
+    uint32_t acc_end;      // final states are exactly [H, acc_end) when H > 0
+    uint32_t table_words;  // LDS_FULL: n_states * n_cols
+    uint32_t hash_shift;   // hashed classes: column = (b >> shift) & (n_cols - 1)
+    uint32_t letters_lo, letters_hi;  // the letter owning each hashed column
+    const uint32_t *dfa;
+    const uint16_t *hot_rows;
+    const uint8_t *cmap;
+    const uint32_t *out_off, *out_ids;
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+};
+
+// Entry of (s, c) in the canonical 32-bit form: successor | kAccept if final.
+template <int PLACE, int LOG2C>
+__device__ __forceinline__ uint32_t lookup(uint32_t s, uint32_t c, const DfaArgs &a,
+                                           const uint32_t *s_tab, const uint16_t *s_hot) {
+    const uint32_t idx = LOG2C >= 0 ? ((s << (LOG2C >= 0 ? LOG2C : 0)) | c) : (s * a.n_cols + c);
+    if constexpr (PLACE == AC_PLACE_LDS_FULL) {
+        return s_tab[idx];
+    } else if constexpr (PLACE == AC_PLACE_LDS_HOT) {
+        if (s < a.hot) {
+            const uint32_t t = s_hot[idx];
+            return t | (t - a.hot < a.acc_end - a.hot ? kAccept : 0u);
+        }
+        return a.dfa[idx];
+    } else {
+        return a.dfa[idx];
+    }
+}
+
+// One byte with the general byte map: bytes in no pattern reset to the root.
+template <int PLACE, int LOG2C>
+__device__ __forceinline__ uint32_t step_byte(uint32_t s, uint32_t b, const DfaArgs &a,
+                                              const uint8_t *s_cmap, const uint32_t *s_tab,
+                                              const uint16_t *s_hot) {
+    const uint32_t c = s_cmap[b];
+    const bool valid = c != kNoClassDev;
+    const uint32_t e = lookup<PLACE, LOG2C>(s & kStateMask, valid ? c : 0u, a, s_tab, s_hot);
+    return valid ? e : 0u;
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int d) {
+    return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
+}
+
+// Walk 16 bytes from state s with the byte map; report final states at
+// positions >= own_lo when `report`. Returns the state after the last byte.
+// (Bytes are taken from each word by shifting, never by a runtime index,
+// so the group stays in registers.)
+template <int PLACE, int LOG2C>
+__device__ __forceinline__ uint32_t walk_group_slow(uint32_t s, const uint4 &v, uint32_t pos,
+                                                    uint32_t own_lo, bool report, const DfaArgs &a,
+                                                    const uint8_t *s_cmap, const uint32_t *s_tab,
+                                                    const uint16_t *s_hot, Emitter &em) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint32_t w = word_of(v, d);
+#pragma unroll 1
+        for (uint32_t j = 0; j < 4; ++j, w >>= 8) {
+            const uint32_t e = step_byte<PLACE, LOG2C>(s, w & 0xffu, a, s_cmap, s_tab, s_hot);
+            s = e & kStateMask;
+            const uint32_t p = pos + 4u * d + j;
+            emit_set(em, report && (e & kAccept) && p >= own_lo, s, uint64_t(p), a.out_off, a.out_ids);
+        }
+    }
+    return s;
+}
+
+// A block of G 16-byte groups of text held in registers.
+template <int G>
+struct TextBlock {
+    uint4 g[G];
+};
+
+template <int G>
+__device__ __forceinline__ void load_block(TextBlock<G> &b, const uint8_t *text, uint32_t p, bool ok) {
+    if (ok) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(text + p);
+#pragma unroll
+        for (int i = 0; i < G; ++i) b.g[i] = q[i];
+    }
+}
+
+// The walkers of one lane, stepping K chunks in lockstep.
+template <int PLACE, int K, int LOG2C, bool HASHED>
+struct Walkers {
+    const DfaArgs &a;
+    const uint8_t *s_cmap;
+    const uint32_t *s_tab;
+    const uint16_t *s_hot;
+    Emitter &em;
+
+    // One 16-byte group per walker. Dead walkers (live false) keep their state.
+    __device__ __forceinline__ void group(uint32_t (&s)[K], const uint4 (&v)[K],
+                                          const uint32_t (&gpos)[K], const bool (&live)[K],
+                                          const uint32_t (&own)[K]) const {
+        uint32_t s0[K], flag[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            s0[k] = s[k];
+            flag[k] = 0;
+        }
+        bool slow = true;
+        uint4 h[K];
+        if constexpr (HASHED) {
+            const uint32_t mask4 = ((1u << LOG2C) - 1u) * 0x01010101u;
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                h[k].x = (v[k].x >> a.hash_shift) & mask4;
+                h[k].y = (v[k].y >> a.hash_shift) & mask4;
+                h[k].z = (v[k].z >> a.hash_shift) & mask4;
+                h[k].w = (v[k].w >> a.hash_shift) & mask4;
+                // a byte is in the alphabet iff it equals the letter owning its bit field
+                const uint32_t d = (__builtin_amdgcn_perm(a.letters_hi, a.letters_lo, h[k].x) ^ v[k].x) |
+                                   (__builtin_amdgcn_perm(a.letters_hi, a.letters_lo, h[k].y) ^ v[k].y) |
+                                   (__builtin_amdgcn_perm(a.letters_hi, a.letters_lo, h[k].z) ^ v[k].z) |
+                                   (__builtin_amdgcn_perm(a.letters_hi, a.letters_lo, h[k].w) ^ v[k].w);
+                bad |= live[k] && d != 0;
+            }
+            slow = __any(bad);
+        }
+        if (slow) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    uint32_t w = word_of(v[k], d);
+#pragma unroll 1
+                    for (uint32_t j = 0; j < 4; ++j, w >>= 8) {
+                        const uint32_t e = step_byte<PLACE, LOG2C>(s[k], w & 0xffu, a, s_cmap, s_tab, s_hot);
+                        s[k] = e & kStateMask;
+                        flag[k] |= e;
+                    }
+                }
+            }
+        } else if constexpr (HASHED) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t sh = (j & 3) * 8;
+                uint32_t c[K], e[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t hw = j < 4 ? h[k].x : j < 8 ? h[k].y : j < 12 ? h[k].z : h[k].w;
+                    c[k] = (hw >> sh) & ((1u << LOG2C) - 1u);
+                }
+                if constexpr (PLACE == AC_PLACE_LDS_HOT) {
+                    // Image rows hold plain successor ids; a state >= H is cold
+                    // or final. Those lanes look the step up in the 32-bit table
+                    // and note whether the state they stand in is final (it was
+                    // entered at byte j-1; byte 15's state is checked below).
+                    bool cold = false;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        cold |= s[k] >= a.hot;
+                        const uint32_t off = (min(s[k], a.hot - 1u) << (LOG2C + 1)) | (c[k] << 1);
+                        e[k] = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(s_hot) + off);
+                    }
+                    if (__any(cold)) {
+                        // all K loads go out before any is waited on; hot lanes
+                        // read entry 0, one shared line
+                        uint32_t g[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            g[k] = a.dfa[s[k] >= a.hot ? ((s[k] << LOG2C) | c[k]) : 0u];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const bool ck = s[k] >= a.hot;
+                            if (j > 0 && ck && s[k] < a.acc_end) flag[k] |= kAccept;
+                            e[k] = ck ? (g[k] & kStateMask) : e[k];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) e[k] = lookup<PLACE, LOG2C>(s[k], c[k], a, s_tab, s_hot);
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if constexpr (PLACE == AC_PLACE_LDS_HOT) {
+                        s[k] = e[k];
+                    } else {
+                        s[k] = e[k] & kStateMask;
+                        flag[k] |= e[k];
+                    }
+                }
+            }
+            if constexpr (PLACE == AC_PLACE_LDS_HOT) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (s[k] - a.hot < a.acc_end - a.hot) flag[k] |= kAccept;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!live[k]) s[k] = s0[k];
+            // the group passed a final state: walk it again and report
+            const bool rep = live[k] && (flag[k] & kAccept);
+            if (__any(rep))
+                walk_group_slow<PLACE, LOG2C>(s0[k], v[k], gpos[k], own[k], rep, a, s_cmap, s_tab, s_hot, em);
+        }
+    }
+
+    template <int GI, int G>
+    __device__ __forceinline__ void group_of(const TextBlock<G> (&X)[K], uint32_t (&s)[K],
+                                             const uint32_t (&own)[K], const uint32_t (&wstart)[K],
+                                             const uint32_t (&bpos)[K], const uint32_t (&bend)[K]) const {
+        uint4 v[K];
+        uint32_t gpos[K];
+        bool live[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] = X[k].g[GI];
+            gpos[k] = bpos[k] + 16u * GI;
+            live[k] = bpos[k] < bend[k] && gpos[k] >= wstart[k];
+        }
+        group(s, v, gpos, live, own);
+    }
+
+    // The groups of the block in X (G groups of 16 bytes), then refill X with
+    // the block `ahead` bytes on (two blocks on when another buffer holds the
+    // next one, one block on when X is the only buffer).
+    template <int G>
+    __device__ __forceinline__ void block(TextBlock<G> (&X)[K], uint32_t (&s)[K], const uint32_t (&own)[K],
+                                          const uint32_t (&wstart)[K], uint32_t (&bpos)[K],
+                                          const uint32_t (&bend)[K], uint32_t ahead) const {
+        // (groups written out one by one: a runtime group index would push X to scratch)
+        group_of<0>(X, s, own, wstart, bpos, bend);
+        group_of<1>(X, s, own, wstart, bpos, bend);
+        group_of<2>(X, s, own, wstart, bpos, bend);
+        group_of<3>(X, s, own, wstart, bpos, bend);
+        if constexpr (G == 8) {
+            group_of<4>(X, s, own, wstart, bpos, bend);
+            group_of<5>(X, s, own, wstart, bpos, bend);
+            group_of<6>(X, s, own, wstart, bpos, bend);
+            group_of<7>(X, s, own, wstart, bpos, bend);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool more = bpos[k] < bend[k];
+            const bool fetch = more && bend[k] - bpos[k] > ahead;  // bpos + ahead < bend
+            const uint32_t next = bpos[k] + ahead;
+            bpos[k] += more ? uint32_t(16 * G) : 0u;
+            load_block(X[k], a.text, next, fetch);
+        }
+    }
+};
+
+// Text is read per walker in blocks of G 16-byte groups (64 or 128 bytes: a
+// half or a whole cache line, loaded back to back). With NBUF = 2 two register
+// buffers are used in turn, so one block is in flight while the other is
+// walked; with NBUF = 1 the next block is requested as soon as a block is
+// finished (fewer registers, and whole lines are never fetched twice).
+template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
+__global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
+    constexpr uint32_t BB = 16u * G;  // bytes per block
+    // LDS: per-wave match queues | byte map (256 B) | table image
+    extern __shared__ __align__(16) uint8_t smem[];
+    constexpr uint32_t kQueues = (BLOCK / 64) * kQueueBytesPerWave;
+    uint8_t *s_cmap = smem + kQueues;
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + kQueues + 256);
+    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + kQueues + 256);
+    const uint32_t tid = threadIdx.x;
+    Emitter em;
+    em.init(smem, a.out, a.cap, a.count);
+    for (uint32_t i = tid; i < 64; i += BLOCK)
+        reinterpret_cast<uint32_t *>(s_cmap)[i] = reinterpret_cast<const uint32_t *>(a.cmap)[i];
+    if constexpr (PLACE == AC_PLACE_LDS_FULL) {
+        for (uint32_t i = tid; i < a.table_words; i += BLOCK) s_tab[i] = a.dfa[i];
+    } else if constexpr (PLACE == AC_PLACE_LDS_HOT) {
+        const uint32_t words = (a.hot * a.n_cols + 1) / 2;  // image is padded to 4 bytes
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.hot_rows);
+        for (uint32_t i = tid; i < words; i += BLOCK) reinterpret_cast<uint32_t *>(s_hot)[i] = src[i];
+    }
+    __syncthreads();
+
+    const Walkers<PLACE, K, LOG2C, HASHED> W{a, s_cmap, s_tab, s_hot, em};
+    const uint32_t lanes = gridDim.x * BLOCK;
+    const uint32_t lane = blockIdx.x * BLOCK + tid;
+
+    for (uint32_t base = 0; base < a.n_chunks; base += K * lanes) {
+        // walker k: chunk `base + k * lanes + lane`, owning [own, hi); it walks
+        // [wstart, hi) with wstart = own - m_max + 1 rounded down to 16 bytes
+        // (starting earlier than needed only repeats warm-up steps).
+        uint32_t s[K], own[K], hi[K], wstart[K], bpos[K], bend[K];
+        TextBlock<G> A[K], B[NBUF == 2 ? K : 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t ch = base + k * lanes + lane;
+            const bool act = ch < a.n_chunks;
+            own[k] = act ? ch * a.chunk : 0u;
+            hi[k] = act ? uint32_t(min(uint64_t(own[k]) + a.chunk, uint64_t(a.n))) : 0u;
+            wstart[k] = (own[k] > a.back ? own[k] - a.back : 0u) & ~15u;
+            bpos[k] = wstart[k] & ~(BB - 1);
+            bend[k] = hi[k] & ~(BB - 1);
+            s[k] = 0;
+            load_block(A[k], a.text, bpos[k], bpos[k] < bend[k]);
+            if constexpr (NBUF == 2)
+                load_block(B[k], a.text, bpos[k] + BB, bend[k] > BB && bpos[k] < bend[k] - BB);
+        }
+        while (true) {
+            bool any_left = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) any_left |= bpos[k] < bend[k];
+            if (!__any(any_left)) break;
+            W.block(A, s, own, wstart, bpos, bend, NBUF * BB);
+            if constexpr (NBUF == 2) {
+                any_left = false;
+#pragma unroll
+                for (int k = 0; k < K; ++k) any_left |= bpos[k] < bend[k];
+                if (!__any(any_left)) break;
+                W.block(B, s, own, wstart, bpos, bend, 2 * BB);
+            }
+        }
+        // bytes past the last full block (chunks whose end is not block-aligned),
+        // or the whole walk when the chunk has no full block
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (base + k * lanes + lane < a.n_chunks) {
+                for (uint32_t p = max(bend[k], wstart[k]); p < hi[k]; ++p) {
+                    const uint32_t e = step_byte<PLACE, LOG2C>(s[k], a.text[p], a, s_cmap, s_tab, s_hot);
+                    s[k] = e & kStateMask;
+                    emit_set(em, (e & kAccept) && p >= own[k], s[k], uint64_t(p), a.out_off, a.out_ids);
+                }
+            }
+        }
+    }
+    em.flush();
+}
+
+using DfaKernel = void (*)(DfaArgs);
+
+// Kernel for one walker count, block size and class scheme of a placement.
+// KIND: 0 = 64-byte blocks, two buffers; 1 = 128-byte blocks, one buffer;
+// 2 = 64-byte blocks, one buffer (four walkers).
+template <int PLACE>
+DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) {
+    const bool hashed = dm.hashed;
+    const int l2 = hashed ? int(dm.log2_cols) : -1;
+    constexpr bool kHot = PLACE == AC_PLACE_LDS_HOT;
+#define AC_DFA_V(KK, LL, HH, NB, GG)                                                                \
+    return dfa_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
+#define AC_DFA_CASE(KK, LL, HH)                                                                     \
+    if (K == KK && l2 == LL && hashed == HH) {                                                      \
+        if constexpr (KK == 4) { AC_DFA_V(KK, LL, HH, 1, 4) }                                       \
+        else if (block_bytes == 128) { AC_DFA_V(KK, LL, HH, 1, 8) }                                 \
+        else { AC_DFA_V(KK, LL, HH, 2, 4) }                                                         \
+    }
+#define AC_DFA_KS(LL, HH) AC_DFA_CASE(1, LL, HH) AC_DFA_CASE(2, LL, HH) AC_DFA_CASE(4, LL, HH)
+    AC_DFA_KS(-1, false)
+    AC_DFA_KS(0, true)
+    AC_DFA_KS(1, true)
+    AC_DFA_KS(2, true)
+    AC_DFA_KS(3, true)
+#undef AC_DFA_KS
+#undef AC_DFA_CASE
+#undef AC_DFA_V
+    return nullptr;
+}
+
+DfaKernel select_global(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
+DfaKernel select_full(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
+DfaKernel select_hot(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
+
+}  // namespace dfa
+}  // namespace acm

@@ -205,10 +205,19 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     out_off[S] = uint32_t(out_ids.size());
     auto accepts = [&](uint32_t b) { return out_off[b + 1] > out_off[b]; };
 
-    // ---- final numbering. With an LDS image, the first `hot` ids go to the
-    // shallowest non-final states (breadth-first order approximates visit
-    // frequency on text unrelated to the patterns), then the other targets of
-    // those rows, so every hot-row entry fits 15 bits; then the rest.
+    // ---- final numbering, in ranges:
+    //   [0, H)                 hot: non-final states whose rows form the 16-bit
+    //                          LDS image, the shallowest first (breadth-first
+    //                          order approximates visit frequency on text
+    //                          unrelated to the patterns); the root is 0;
+    //   [H, term_end)          final states where some pattern ends exactly;
+    //   [term_end, acc_end)    final states whose outputs all come by failure;
+    //   [acc_end, S)           the other non-final states, those that a hot row
+    //                          leads to first.
+    // A step into a state >= H is then the one event the scan kernels must
+    // look at, and "final" and "pattern ends here" are range tests. Every
+    // successor of a hot row must fit the 16-bit entries: the image shrinks
+    // until it does (or is dropped if the final states alone do not fit).
     uint32_t hot_budget = 0;
     if (plan.lds_bytes > 256) {
         const bool full_fits = 256ull + uint64_t(S) * C * 4ull <= plan.lds_bytes;
@@ -217,37 +226,62 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
             if (plan.max_states) hot_budget = std::min(hot_budget, plan.max_states);
         }
     }
-    std::vector<uint32_t> perm(S);  // bfs id -> final id
-    uint32_t H = 0;
-    if (hot_budget > 0) {
-        std::vector<uint32_t> cand;
-        for (uint32_t b = 0; b < S && cand.size() < std::min<uint32_t>(hot_budget, kHotIdLimit); ++b)
-            if (!accepts(b)) cand.push_back(b);
-        H = uint32_t(cand.size());
-        std::vector<uint8_t> mark(S);
-        while (H > 0) {
-            std::fill(mark.begin(), mark.end(), 0);
-            for (uint32_t i = 0; i < H; ++i) mark[cand[i]] = 1;
-            uint32_t extra = 0;
+    auto terminal = [&](uint32_t b) { return own_off[b + 1] > own_off[b]; };
+    uint32_t A = 0, T = 0;
+    for (uint32_t b = 0; b < S; ++b) {
+        A += accepts(b);
+        T += terminal(b);
+    }
+    std::vector<uint32_t> cand;  // non-final states in breadth-first order (the root first)
+    const uint32_t want = std::max<uint32_t>(1, std::min<uint32_t>(hot_budget, kHotIdLimit));
+    for (uint32_t b = 0; b < S && cand.size() < want; ++b)
+        if (!accepts(b)) cand.push_back(b);
+    uint32_t H = uint32_t(cand.size());
+    std::vector<uint8_t> mark(S, 0);  // 1 = hot, 2 = non-final target of a hot row
+    bool image = hot_budget > 0;
+    while (true) {
+        std::fill(mark.begin(), mark.end(), 0);
+        for (uint32_t i = 0; i < H; ++i) mark[cand[i]] = 1;
+        uint32_t extra = 0;
+        if (image)
             for (uint32_t i = 0; i < H; ++i)
                 for (uint32_t c = 0; c < C; ++c) {
-                    uint32_t t = delta[size_t(cand[i]) * C + c];
-                    if (!mark[t]) { mark[t] = 2; ++extra; }
+                    const uint32_t t = delta[size_t(cand[i]) * C + c];
+                    if (!mark[t] && !accepts(t)) {
+                        mark[t] = 2;
+                        ++extra;
+                    }
                 }
-            if (H + extra <= kHotIdLimit) break;
-            H -= std::max<uint32_t>(1, (H + extra - kHotIdLimit + 1) / 2);
+        if (image && H < kMinHotStates && H < want) {
+            image = false;  // too few rows left to be worth an LDS image
+            H = 1;
+            continue;
         }
-        if (H > 0) {
-            uint32_t next = 0;
-            for (uint32_t i = 0; i < H; ++i) perm[cand[i]] = next++;
-            for (uint32_t b = 0; b < S; ++b)
-                if (mark[b] == 2) perm[b] = next++;
-            for (uint32_t b = 0; b < S; ++b)
-                if (!mark[b]) perm[b] = next++;
+        if (!image || uint64_t(H) + A + extra <= kHotIdLimit) break;
+        if (H == 1 || uint64_t(A) + 1 > kHotIdLimit) {
+            image = false;  // the final states alone overflow 16-bit ids
+            H = 1;
+            continue;
         }
+        const uint64_t cut = std::max<uint64_t>(1, (uint64_t(H) + A + extra - kHotIdLimit + 1) / 2);
+        H = cut >= H ? 1u : uint32_t(H - cut);
     }
-    if (H == 0)
-        for (uint32_t b = 0; b < S; ++b) perm[b] = b;
+    std::vector<uint32_t> perm(S);  // bfs id -> final id
+    {
+        uint32_t next = 0;
+        for (uint32_t i = 0; i < H; ++i) perm[cand[i]] = next++;
+        for (uint32_t b = 0; b < S; ++b)
+            if (!mark[b] && terminal(b)) perm[b] = next++;
+        for (uint32_t b = 0; b < S; ++b)
+            if (!mark[b] && accepts(b) && !terminal(b)) perm[b] = next++;
+        for (uint32_t b = 0; b < S; ++b)
+            if (mark[b] == 2) perm[b] = next++;
+        for (uint32_t b = 0; b < S; ++b)
+            if (!mark[b] && !accepts(b)) perm[b] = next++;
+    }
+    m.term_end = H + T;
+    m.acc_end = H + A;
+    if (!image) H = 0;  // numbering keeps the root alone in front; no image rows
     std::vector<uint32_t> inv(S);
     for (uint32_t b = 0; b < S; ++b) inv[perm[b]] = b;
 
@@ -280,11 +314,9 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     m.hot_go.assign(size_t(H) * C, 0);
     for (uint32_t f = 0; f < H; ++f)
         for (uint32_t c = 0; c < C; ++c) {
-            uint32_t e = m.dfa[size_t(f) * C + c];
-            uint32_t g = m.go[size_t(f) * C + c];
-            // (successors of hot rows were numbered below kHotIdLimit above)
-            m.hot_dfa[size_t(f) * C + c] = uint16_t((e & kStateMask) | ((e & kAccept) ? kHotAccept : 0));
-            m.hot_go[size_t(f) * C + c] = uint16_t((g & kStateMask) | ((g & kAccept) ? kHotAccept : 0));
+            // successors of hot rows were numbered below kHotIdLimit above
+            m.hot_dfa[size_t(f) * C + c] = uint16_t(m.dfa[size_t(f) * C + c] & kStateMask);
+            m.hot_go[size_t(f) * C + c] = uint16_t(m.go[size_t(f) * C + c] & kStateMask);
         }
     // 16-bit images are copied as 32-bit words: pad them to whole words
     if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);

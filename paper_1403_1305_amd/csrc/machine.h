@@ -19,10 +19,10 @@ namespace acm {
 // output set is non-empty (it is a final state).
 constexpr uint32_t kAccept = 0x80000000u;
 constexpr uint32_t kStateMask = 0x7fffffffu;
-// 16-bit LDS image entries: successor id (< 2^15), top bit as above.
-constexpr uint16_t kHotAccept = 0x8000u;
-constexpr uint16_t kHotMask = 0x7fffu;
-constexpr uint32_t kHotIdLimit = 1u << 15;
+// 16-bit LDS image entries hold plain successor ids, which must be < 2^16.
+constexpr uint32_t kHotIdLimit = 1u << 16;
+// An image squeezed below this many rows (to fit the id limit) is dropped.
+constexpr uint32_t kMinHotStates = 256;
 // byte -> column map value for bytes that occur in no pattern
 constexpr uint8_t kNoClass = 0xffu;
 
@@ -49,11 +49,17 @@ struct Machine {
     // Patterns ending exactly at each state (no failure-chain outputs).
     std::vector<uint32_t> own_off, own_ids;
 
+    // State ids come in ranges: [0, H) non-final states with image rows,
+    // [H, term_end) final states where a pattern ends exactly, [term_end,
+    // acc_end) final states with inherited outputs only, then the other
+    // non-final states. H = hot_states (at least 1 for the numbering even
+    // without an image, since the root comes first).
+    uint32_t term_end = 0, acc_end = 0;
     // States [0, hot_states) form the LDS image; every successor of a hot
-    // row is numbered below kHotIdLimit so that it fits 15 bits.
+    // row is numbered below kHotIdLimit so that it fits 16 bits.
     uint32_t hot_states = 0;
-    std::vector<uint16_t> hot_dfa;  // hot_states * n_cols, as dfa but 16-bit
-    std::vector<uint16_t> hot_go;   // hot_states * n_cols, as go but 16-bit
+    std::vector<uint16_t> hot_dfa;  // hot_states * n_cols successor ids
+    std::vector<uint16_t> hot_go;   // hot_states * n_cols goto children, 0 = no edge
     double build_ms = 0.0;
 };
 

@@ -12,6 +12,7 @@ namespace acm {
 // owned by the automaton.
 struct DeviceMachine {
     uint32_t n_states = 0, n_cols = 0, m_max = 0, hot_states = 0;
+    uint32_t term_end = 0, acc_end = 0;  // state id ranges (see Machine)
     uint32_t log2_cols = 0, hash_shift = 0;
     bool cols_pow2 = false, hashed = false;
     uint8_t hash_letter[8] = {0};
@@ -27,6 +28,7 @@ struct ScanConfig {
     uint32_t chunk = 0;      // DFA chunk bytes (multiple of 16), 0 = auto
     uint32_t block = 0;      // threads per workgroup, 0 = auto
     uint32_t walkers = 0;    // DFA chunks walked per lane (1, 2, 4), 0 = auto
+    uint32_t block_bytes = 0;  // DFA text bytes per walker load (64, 128), 0 = auto
     uint32_t placement = 0;  // resolved AC_PLACE_* (never AUTO here)
 };
 

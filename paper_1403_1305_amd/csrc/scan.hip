@@ -24,7 +24,8 @@ struct PfacArgs {
     uint64_t n;
     uint32_t m_max;
     uint32_t n_cols;
-    uint32_t hot_states;
+    uint32_t hot_states;  // image rows used (a prefix of the machine's hot rows)
+    uint32_t term_lo, term_end;  // states where a pattern ends exactly
     uint32_t table_words;
     uint32_t halo;  // text bytes staged past the tile's last start
     const uint32_t *go;
@@ -46,8 +47,10 @@ __device__ __forceinline__ uint32_t go_entry(uint32_t s, uint32_t c, const PfacA
         return s_tab[idx];
     } else if constexpr (PLACE == AC_PLACE_LDS_HOT) {
         if (s < a.hot_states) {
-            const uint32_t e = s_hot[idx];
-            return (e & kHotMask) | ((e & kHotAccept) << 16);
+            // image entries are plain child ids (0 = no edge); a pattern ends
+            // exactly at the child iff its id is in [term_lo, term_end)
+            const uint32_t t = s_hot[idx];
+            return t | (t - a.term_lo < a.term_end - a.term_lo ? kAccept : 0u);
         }
         return a.go[idx];
     } else {
@@ -235,6 +238,8 @@ int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     a.m_max = dm.m_max;
     a.n_cols = dm.n_cols;
     a.hot_states = dm.hot_states;
+    a.term_lo = dm.hot_states;
+    a.term_end = dm.term_end;
     a.table_words = dm.n_states * dm.n_cols;
     a.halo = std::min<uint32_t>(dm.m_max, 2048u);
     a.go = dm.go;

@@ -50,10 +50,10 @@ def to_device(text) -> "torch.Tensor":
 
 
 def gpu_keys(auto, text, algo=ac.AC_ALGO_DFA, chunk=0, placement=0, capacity=None,
-             walkers=0) -> np.ndarray:
+             walkers=0, block_bytes=0) -> np.ndarray:
     d = to_device(text) if not isinstance(text, torch.Tensor) else text
     keys = ac.scan_text(auto, d, capacity=capacity,
-                        opts=ac._scan_opts(algo, chunk, 0, placement, walkers))
+                        opts=ac._scan_opts(algo, chunk, 0, placement, walkers, block_bytes))
     return np.sort(ac.keys_to_numpy(keys))
 
 
@@ -109,7 +109,9 @@ def test_small_dna(small, algo, placement):
 def test_small_dna_chunk_lengths(small, chunk, walkers):
     w, expect = small
     a = build(w.patterns)
-    assert np.array_equal(gpu_keys(a, w.text, chunk=chunk, walkers=walkers), expect)
+    for bb in (64, 128):
+        assert np.array_equal(gpu_keys(a, w.text, chunk=chunk, walkers=walkers, block_bytes=bb),
+                              expect), bb
 
 
 def test_determinism(small):
@@ -145,9 +147,10 @@ def test_chunk_boundaries(chunk, m):
     expect = oracle.oracle_match(text, pats)
     for placement in (ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_HOT):
         a = build(pats, placement=placement, hot_states=7 if placement == ac.AC_PLACE_LDS_HOT else 0)
-        for walkers in ((1, 2) if placement == ac.AC_PLACE_LDS_HOT else (1, 2, 4)):
-            assert np.array_equal(gpu_keys(a, text, chunk=chunk, walkers=walkers), expect), \
-                (chunk, m, placement, walkers)
+        for walkers in (1, 2, 4):
+            for bb in (64, 128):
+                assert np.array_equal(gpu_keys(a, text, chunk=chunk, walkers=walkers, block_bytes=bb),
+                                      expect), (chunk, m, placement, walkers, bb)
     a = build(pats)
     assert np.array_equal(gpu_keys(a, text, algo=ac.AC_ALGO_PFAC), expect)
 
@@ -161,12 +164,13 @@ def test_ragged_and_tiny_texts(n):
         a = build(pats, placement=placement)
         for algo in (ac.AC_ALGO_DFA, ac.AC_ALGO_PFAC):
             for chunk in (0, 16, 32):
-                for walkers in (((1, 2) if placement == ac.AC_PLACE_LDS_HOT else (1, 2, 4))
-                                if algo == ac.AC_ALGO_DFA else (0,)):
+                for walkers in ((1, 2, 4) if algo == ac.AC_ALGO_DFA else (0,)):
                     if algo == ac.AC_ALGO_PFAC and chunk:
                         continue
-                    assert np.array_equal(gpu_keys(a, text, algo=algo, chunk=chunk, walkers=walkers),
-                                          expect), (n, placement, algo, chunk, walkers)
+                    for bb in ((64, 128) if algo == ac.AC_ALGO_DFA else (0,)):
+                        assert np.array_equal(gpu_keys(a, text, algo=algo, chunk=chunk, walkers=walkers,
+                                                       block_bytes=bb),
+                                              expect), (n, placement, algo, chunk, walkers, bb)
 
 
 def test_bytes_outside_the_alphabet():

@@ -121,12 +121,16 @@ def check_invariants(t: Tables, patterns):
         assert (t.cmap[b] != 255) == (b in alphabet)
         if b in alphabet:
             assert t.cmap[b] < C
+    # ids come in ranges: image rows, final states with own patterns, other
+    # final states, the rest (the root alone in front when there is no image)
     H = t.info["hot_states"]
+    lo = H if H else 1
+    A, T = int(accept.sum()), int(own.sum())
+    assert np.array_equal(np.nonzero(own)[0], np.arange(lo, lo + T))
+    assert np.array_equal(np.nonzero(accept)[0], np.arange(lo, lo + A))
     if H:
-        assert (t.hot & 0x7FFF).max() < (1 << 15)
-        assert np.array_equal((t.hot & 0x7FFF).astype(np.uint32), t.dfa[:H] & 0x7FFFFFFF)
-        assert np.array_equal((t.hot >> 15).astype(np.uint32), t.dfa[:H] >> 31)
-        assert np.array_equal((t.hot_go & 0x7FFF).astype(np.uint32), t.go[:H] & 0x7FFFFFFF)
+        assert np.array_equal(t.hot.astype(np.uint32), t.dfa[:H] & 0x7FFFFFFF)
+        assert np.array_equal(t.hot_go.astype(np.uint32), t.go[:H] & 0x7FFFFFFF)
         assert not accept[:H].any()  # final states are never in the image
 
 
@@ -198,3 +202,20 @@ def test_hot_image_for_large_dna_set():
     check_invariants(t, w.patterns)
     text = w.text[:2000].tobytes()
     assert np.array_equal(t.dfa_walk(text), oracle.oracle_match(text, w.patterns))
+
+
+def test_large_protein_set_builds():
+    """50,000 protein patterns: more final states than 16-bit ids can hold
+    beside an image, so the build must fall back cleanly (no image)."""
+    w = plain_workload("protein1g", n=1 << 16)
+    t = Tables(build_host(w.patterns))
+    info = t.info
+    assert info["n_cols"] == 20 and info["n_states"] > 100_000
+    accept = np.diff(t.out_off.astype(np.int64)) > 0
+    lo = info["hot_states"] if info["hot_states"] else 1
+    assert np.array_equal(np.nonzero(accept)[0], np.arange(lo, lo + int(accept.sum())))
+    text = w.text[:1500].tobytes()
+    assert np.array_equal(t.dfa_walk(text), oracle.oracle_match(text, w.patterns))
+    # forcing the hot placement keeps whatever image fits
+    t2 = Tables(build_host(w.patterns, placement=ac.AC_PLACE_LDS_HOT))
+    assert np.array_equal(t2.dfa_walk(text), oracle.oracle_match(text, w.patterns))
