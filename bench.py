@@ -51,6 +51,32 @@ def time_steps(fn, steps, stream, torch):
     return wall, ms
 
 
+KERNEL_SOURCES = ["paper_1403_1305_amd/csrc/dfa_kernel.h", "paper_1403_1305_amd/csrc/device_common.h",
+                  "paper_1403_1305_amd/csrc/dfa.hip"]
+PROFILE = os.path.join(ROOT, "profiles", "dfa_scan_dna256m.md")
+
+
+def profiled_traffic(workload):
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
+    or None when the summary is for another workload or the kernel sources
+    have changed since the counters were taken."""
+    import hashlib
+    if workload != "dna256m" or not os.path.exists(PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    for line in open(PROFILE):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, sample_bytes):
     import oracle
     ac_cpu = oracle.OracleAC(w.patterns)
@@ -172,7 +198,8 @@ def main():
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "matches": matches,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic(args.workload)},
         "kernel_ms": round(kernel_ms, 4),
         "build_ms": round(info["build_ms"], 2),
         "build_upload_ms": round(build_wall_ms, 2),
