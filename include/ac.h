@@ -178,6 +178,32 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
             uint64_t capacity, uint64_t *d_count, const ac_scan_opts *opts, void *stream);
 
 /*
+ * ac_scan_stream -- continue a text that arrives in pieces (the per-buffer
+ * search of the paper's Alg. 1, with the machine's state carried from one
+ * buffer to the next, so occurrences that span pieces are found).
+ * Asynchronous on `stream`; DFA scan only.
+ *
+ *   d_text, n     device, this piece (16-byte aligned)
+ *   base          position of the piece's first byte in the whole text;
+ *                 matches are reported as (base + local end) << 32 | id,
+ *                 and base + n must stay below 2^32
+ *   d_state_in    device uint32: the state the previous piece ended in, as
+ *                 written to its d_state_out; NULL for the first piece (root)
+ *   d_state_out   device uint32 (NULL = not wanted): receives the state after
+ *                 the piece's last byte. The value is an opaque token of this
+ *                 automaton. Must not alias d_state_in.
+ *   append        nonzero: add to *d_count and the keys already in d_matches
+ *                 instead of starting from zero (one list for all pieces)
+ *
+ * Errors: as ac_scan, plus AC_ERR_INVALID for an algo other than
+ * AC_ALGO_DFA or aliased state words.
+ */
+int ac_scan_stream(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t base,
+                   const uint32_t *d_state_in, uint32_t *d_state_out, uint64_t *d_matches,
+                   uint64_t capacity, uint64_t *d_count, int append, const ac_scan_opts *opts,
+                   void *stream);
+
+/*
  * ac_scan_sync -- ac_scan, then wait for `stream` and copy the total count to
  * *h_count. Returns AC_ERR_OVERFLOW if the total exceeds capacity (the first
  * `capacity` keys are still valid).

@@ -82,6 +82,8 @@ SIGNATURES = {
     "ac_scan": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, ctypes.POINTER(ac_scan_opts), _vp]),
     "ac_scan_sync": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, ctypes.POINTER(ac_scan_opts),
                                     _vp, ctypes.POINTER(_u64)]),
+    "ac_scan_stream": (ctypes.c_int, [_vp, _vp, _u64, _u64, _vp, _vp, _vp, _u64, _vp, ctypes.c_int,
+                                      ctypes.POINTER(ac_scan_opts), _vp]),
     "ac_sort_scratch_bytes": (_u64, [_u64]),
     "ac_sort_matches": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp]),
     "ac_last_error": (ctypes.c_char_p, []),
@@ -228,6 +230,16 @@ def ac_scan_sync(a: Automaton, d_text, n: int, d_matches, capacity: int, d_count
                                        ctypes.byref(opts) if opts is not None else None,
                                        _stream(stream), ctypes.byref(h)))
     return h.value
+
+
+def ac_scan_stream(a: Automaton, d_text, n: int, base: int, d_state_in, d_state_out, d_matches,
+                   capacity: int, d_count, append: bool = False, opts: ac_scan_opts | None = None,
+                   stream=None) -> None:
+    _check(load_library().ac_scan_stream(a.handle, _ptr(d_text), n, base, _ptr(d_state_in),
+                                         _ptr(d_state_out), _ptr(d_matches), capacity, _ptr(d_count),
+                                         int(bool(append)),
+                                         ctypes.byref(opts) if opts is not None else None,
+                                         _stream(stream)))
 
 
 def ac_sort_scratch_bytes(count: int) -> int:

@@ -257,6 +257,48 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
     return rc == AC_OK ? AC_OK : fail(rc, err);
 }
 
+int ac_scan_stream(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t base,
+                   const uint32_t *d_state_in, uint32_t *d_state_out, uint64_t *d_matches,
+                   uint64_t capacity, uint64_t *d_count, int append, const ac_scan_opts *opts,
+                   void *stream) {
+    if (!a || !d_count) return fail(AC_ERR_INVALID, "ac_scan_stream: NULL automaton or count");
+    if (!a->on_device) return fail(AC_ERR_INVALID, "ac_scan_stream: automaton has no device tables");
+    if (n > 0 && !d_text) return fail(AC_ERR_INVALID, "ac_scan_stream: NULL text");
+    if (capacity > 0 && !d_matches) return fail(AC_ERR_INVALID, "ac_scan_stream: NULL match buffer");
+    if (base + n >= (1ull << 32) || base >= (1ull << 32))
+        return fail(AC_ERR_TOO_LARGE, "ac_scan_stream: positions must stay below 2^32");
+    if (n > 0 && (reinterpret_cast<uintptr_t>(d_text) & 15u))
+        return fail(AC_ERR_INVALID, "ac_scan_stream: text must be 16-byte aligned");
+    if (d_state_in && d_state_in == d_state_out)
+        return fail(AC_ERR_INVALID, "ac_scan_stream: state_in and state_out must differ");
+    acm::ScanConfig cfg;
+    uint32_t want = AC_PLACE_AUTO;
+    if (opts) {
+        if (opts->algo != AC_ALGO_DFA)
+            return fail(AC_ERR_INVALID, "ac_scan_stream: only the DFA scan carries state");
+        cfg.chunk = opts->chunk;
+        cfg.block = opts->block;
+        cfg.walkers = opts->walkers;
+        cfg.block_bytes = opts->block_bytes;
+        want = opts->placement;
+    }
+    if (!resolve_placement(a, want, cfg.placement))
+        return fail(AC_ERR_INVALID, "ac_scan_stream: placement not available for this automaton");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != a->device)
+        return fail(AC_ERR_INVALID, "ac_scan_stream: automaton lives on another device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::string err;
+    int rc = append ? AC_OK : acm::launch_zero_count(d_count, s, err);
+    acm::StreamArgs st;
+    st.base = base;
+    st.state_in = d_state_in;
+    st.state_out = d_state_out;
+    if (rc == AC_OK)
+        rc = acm::launch_dfa_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err, st);
+    return rc == AC_OK ? AC_OK : fail(rc, err);
+}
+
 int ac_scan_sync(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_matches,
                  uint64_t capacity, uint64_t *d_count, const ac_scan_opts *opts, void *stream,
                  uint64_t *h_count) {

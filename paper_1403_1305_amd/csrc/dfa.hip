@@ -16,10 +16,18 @@ uint32_t block_for(uint32_t placement, uint32_t K) {
 
 }  // namespace
 
+__global__ void copy_state_kernel(const uint32_t *in, uint32_t *out) { *out = in ? *in : 0u; }
+
+int launch_copy_state(const uint32_t *in, uint32_t *out, hipStream_t stream, std::string &err) {
+    hipLaunchKernelGGL(copy_state_kernel, dim3(1), dim3(1), 0, stream, in, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? AC_OK : hip_fail(e, "copy_state launch", err);
+}
+
 int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                     uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
-                    std::string &err) {
-    if (n == 0) return AC_OK;
+                    std::string &err, const StreamArgs &st) {
+    if (n == 0) return st.state_out ? launch_copy_state(st.state_in, st.state_out, stream, err) : AC_OK;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     const uint32_t cus = uint32_t(compute_units(dev));
@@ -44,6 +52,9 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
     a.out = out;
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long *>(count);
+    a.base = st.base;
+    a.state_in = st.state_in;
+    a.state_out = st.state_out;
 
     // default walkers per lane: two hide more lookup latency than one except
     // when every lookup goes to global memory

@@ -55,6 +55,9 @@ struct DfaArgs {
     uint64_t *out;
     uint64_t cap;
     unsigned long long *count;
+    uint64_t base;              // added to every reported end position
+    const uint32_t *state_in;   // state before byte 0 (NULL = the root)
+    uint32_t *state_out;        // receives the state after byte n-1 (NULL = not wanted)
 };
 
 // Entry of (s, c) in the canonical 32-bit form: successor | kAccept if final.
@@ -107,7 +110,7 @@ __device__ __forceinline__ uint32_t walk_group_slow(uint32_t s, const uint4 &v, 
             const uint32_t e = step_byte<PLACE, LOG2C>(s, w & 0xffu, a, s_cmap, s_tab, s_hot);
             s = e & kStateMask;
             const uint32_t p = pos + 4u * d + j;
-            emit_set(em, report && (e & kAccept) && p >= own_lo, s, uint64_t(p), a.out_off, a.out_ids);
+            emit_set(em, report && (e & kAccept) && p >= own_lo, s, a.base + p, a.out_off, a.out_ids);
         }
     }
     return s;
@@ -339,7 +342,9 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
             wstart[k] = (own[k] > a.back ? own[k] - a.back : 0u) & ~15u;
             bpos[k] = wstart[k] & ~(BB - 1);
             bend[k] = hi[k] & ~(BB - 1);
-            s[k] = 0;
+            // a walk that would start before byte 0 starts there instead, in the
+            // state the text's earlier pieces ended in (the root for a new text)
+            s[k] = (act && own[k] <= a.back && a.state_in) ? *a.state_in : 0u;
             load_block(A[k], a.text, bpos[k], bpos[k] < bend[k]);
             if constexpr (NBUF == 2)
                 load_block(B[k], a.text, bpos[k] + BB, bend[k] > BB && bpos[k] < bend[k] - BB);
@@ -366,8 +371,11 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
                 for (uint32_t p = max(bend[k], wstart[k]); p < hi[k]; ++p) {
                     const uint32_t e = step_byte<PLACE, LOG2C>(s[k], a.text[p], a, s_cmap, s_tab, s_hot);
                     s[k] = e & kStateMask;
-                    emit_set(em, (e & kAccept) && p >= own[k], s[k], uint64_t(p), a.out_off, a.out_ids);
+                    emit_set(em, (e & kAccept) && p >= own[k], s[k], a.base + p, a.out_off, a.out_ids);
                 }
+                // the last chunk's walker ends exactly in the text's final state:
+                // it walked at least m_max bytes or started from the carried state
+                if (base + k * lanes + lane == a.n_chunks - 1 && a.state_out) *a.state_out = s[k];
             }
         }
     }

@@ -40,9 +40,21 @@ int compute_units(int device);
 // Each returns AC_OK or an AC_ERR_* code with `err` set. Nothing is
 // launched when an error is returned before the first launch.
 int launch_zero_count(uint64_t *d_count, hipStream_t stream, std::string &err);
+// Continuation of a text scanned in pieces (the per-buffer search with carried
+// state of the paper's Alg. 1): positions are reported as base + local
+// position, the walk of byte 0 continues from *state_in, and the state after
+// the last byte is written to *state_out. Both pointers are device memory and
+// may be NULL.
+struct StreamArgs {
+    uint64_t base = 0;
+    const uint32_t *state_in = nullptr;
+    uint32_t *state_out = nullptr;
+};
+
 int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                     uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
-                    std::string &err);
+                    std::string &err, const StreamArgs &st = StreamArgs());
+int launch_copy_state(const uint32_t *in, uint32_t *out, hipStream_t stream, std::string &err);
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                      std::string &err);

@@ -300,3 +300,63 @@ def test_full_dna256m_pfac():
 
 def test_full_protein1g_dfa():
     check_full("protein1g", device_sort=True)
+
+
+# ---------------------------------------------------------------- streaming (carried state)
+
+def stream_scan(auto, text: np.ndarray, cuts, opts=None):
+    """Scan `text` in the pieces between `cuts`, carrying the machine state;
+    returns the sorted keys and the final state token."""
+    total = len(text)
+    out = torch.empty(max(16, total // 8 + 64), dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    states = torch.zeros(2, dtype=torch.int32, device="cuda")
+    bounds = [0] + sorted(cuts) + [total]
+    for i in range(len(bounds) - 1):
+        lo, hi = bounds[i], bounds[i + 1]
+        piece = to_device(text[lo:hi])
+        s_in = None if i == 0 else states[(i - 1) % 2:(i - 1) % 2 + 1]
+        s_out = states[i % 2:i % 2 + 1]
+        ac.ac_scan_stream(auto, piece, hi - lo, lo, s_in, s_out, out, out.numel(), count,
+                          append=i > 0, opts=opts)
+    torch.cuda.synchronize()
+    n = int(count.item())
+    assert n <= out.numel()
+    last = (len(bounds) - 2) % 2
+    return np.sort(ac.keys_to_numpy(out[:n])), int(states[last].item())
+
+
+@pytest.mark.parametrize("placement", [ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_HOT])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_stream_pieces(placement, seed):
+    w = plain_workload("dna1m", n=1 << 17)
+    rng = np.random.default_rng(seed)
+    text = w.text.copy()
+    pats = list(w.patterns) + [b"A" * 12, b"ACGTACGTACGTAC"]
+    # occurrences straddling the cuts: plant some patterns right across them
+    cuts = sorted(set(int(c) for c in rng.integers(1, len(text), size=40)))
+    cuts += [cuts[0] + 1, cuts[0] + 2, cuts[-1]]  # tiny and empty pieces
+    for c in cuts[:10]:
+        p = pats[int(rng.integers(0, len(pats)))]
+        lo = max(0, c - len(p) // 2)
+        text[lo:lo + len(p)] = np.frombuffer(p, dtype=np.uint8)[: len(text) - lo]
+    expect = oracle.oracle_match(text, pats)
+    a = build(pats, placement=placement, hot_states=200 if placement == ac.AC_PLACE_LDS_HOT else 0)
+    whole, st_whole = stream_scan(a, text, [])
+    assert np.array_equal(whole, expect)
+    for chunk in (0, 64, 48):
+        got, st = stream_scan(a, text, cuts, opts=ac._scan_opts(0, chunk, 0, 0, 0))
+        assert np.array_equal(got, expect), chunk
+        assert st == st_whole
+
+
+def test_stream_rejects_pfac_and_aliasing():
+    a = build([b"AB"])
+    d = to_device(b"ABAB" * 8)
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.zeros(64, dtype=torch.int64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(ac.AcError):
+        ac.ac_scan_stream(a, d, 32, 0, None, st, out, 64, count, opts=ac._scan_opts(ac.AC_ALGO_PFAC))
+    with pytest.raises(ac.AcError):
+        ac.ac_scan_stream(a, d, 32, 0, st, st, out, 64, count)
