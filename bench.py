@@ -89,12 +89,106 @@ def cpu_baseline(w, sample_bytes):
                       f"single-threaded failure-link scan ({dt:.1f} s); build not timed"}
 
 
+BATCHED_DESC = ("4,096 i.i.d. uniform ACGT texts, lengths log-uniform in [1 KiB, 4 MiB]; 16 resident "
+                 "pattern sets of 100-20,000 patterns (lengths 8-32), each text naming one at random")
+
+
+def bench_batched(args, torch, ac, stream):
+    """The batched form: one autotuned persistent launch over every text
+    (hipGraph-captured submission), against per-text plain ac_scan launches of
+    the same texts; both lists must agree exactly."""
+    import numpy as np
+
+    from paper_1403_1305_amd import autotune
+    from synth import batched_workload
+
+    log("generate batched")
+    texts, sets, text_set = batched_workload()
+    buf, offs, lens = ac.pack_texts(texts)
+    del texts
+    total = int(lens.sum())
+    t0 = time.perf_counter()
+    autos = []
+    for s in sets:
+        d, o = ac.patterns_csr(s)
+        autos.append(ac.ac_build(d, o, opts=ac._opts(placement=ac.AC_PLACE_LDS_HOT)))
+    build_s = time.perf_counter() - t0
+    states = [ac.ac_info(a)["n_states"] for a in autos]
+    d_text = torch.from_numpy(buf).to("cuda")
+    del buf
+    cap = 1 << 25
+    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    log("tune batched")
+    batch, tune, report = autotune.tune_batch(autos, d_text, offs, lens, text_set, out, cap, count,
+                                              stream=stream, use_cache=False)
+    info = ac.ac_batch_info(batch)
+    log("batched plan", info, report["choice"])
+
+    def step(i, graph=True):
+        ac.ac_batch_scan(batch, d_text, out, cap, count, graph, stream)
+
+    for i in range(args.warmup):
+        step(i)
+    steps = max(3, args.steps // 2)
+    wall, ms = time_steps(step, steps, stream, torch)
+    _, ms_eager = time_steps(lambda i: step(i, False), steps, stream, torch)
+    matches = int(count.item())
+    assert matches <= cap, "batched output buffer too small"
+    keys = np.sort(ac.keys_to_numpy(out[:matches]))
+
+    # per-text plain launches of the same texts, each into its own slice
+    pos = (keys >> np.uint64(32)).astype(np.int64)
+    per_text = np.diff(np.searchsorted(pos, np.append(offs.astype(np.int64), np.int64(1) << 40)))
+    slot = np.concatenate([[0], np.cumsum(per_text)]).astype(np.int64)
+    counts = torch.zeros(len(offs), dtype=torch.int64, device="cuda")
+    out2 = torch.empty(max(1, matches), dtype=torch.int64, device="cuda")
+    popts = ac._scan_opts(ac.AC_ALGO_DFA, 0, 0, 0)
+
+    def plain(i):
+        for t in range(len(offs)):
+            o, n = int(offs[t]), int(lens[t])
+            if n:
+                ac.ac_scan(autos[int(text_set[t])], d_text[o:o + n], n, out2[int(slot[t]):],
+                           int(per_text[t]), counts[t:t + 1], popts, stream)
+
+    plain(0)
+    pwall, pms = time_steps(plain, 2, stream, torch)
+    got = counts.cpu().numpy()
+    exact = bool(np.array_equal(got, per_text))
+    if exact:
+        k2 = ac.keys_to_numpy(out2[:matches]).copy()
+        for t in range(len(offs)):  # positions relative to each text -> batch buffer
+            k2[slot[t]:slot[t + 1]] += np.uint64(int(offs[t])) << np.uint64(32)
+        exact = bool(np.array_equal(np.sort(k2), keys))
+    kernel_ms = float(np.mean(ms))
+    achieved = (total + 8 * matches) / (kernel_ms * 1e-3) / 1e9
+    return {
+        "value": round(total * steps / wall / 1e9, 3), "unit": "GB/s",
+        "workload": f"batched: {BATCHED_DESC}",
+        "n_texts": len(offs), "text_bytes": total, "automata": len(autos),
+        "states_min_max": [min(states), max(states)], "matches": matches,
+        "graph_ms": round(kernel_ms, 4), "eager_ms": round(float(np.mean(ms_eager)), 4),
+        "plan": {k: info[k] for k in ("placement", "walkers", "chunk", "threads", "grid", "n_tasks")},
+        "autotune": {"choice": report["choice"], "tune_s": round(report["tune_s"], 2),
+                     "candidates": len(report.get("candidates", []))},
+        "plain_per_text": {"value": round(total * len(pms) / pwall / 1e9, 3), "unit": "GB/s",
+                           "ms": round(float(np.mean(pms)), 3), "launches": int((lens > 0).sum())},
+        "speedup_vs_plain": round(float(np.mean(pms)) / kernel_ms, 2),
+        "exact_vs_plain": exact,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "build_s": round(build_s, 2),
+    }
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC))
+    p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched"])
+    p.add_argument("--no-batched", action="store_true", help="skip the batched sub-benchmark")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)
@@ -119,6 +213,19 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.workload == "batched":
+        b = bench_batched(args, torch, ac, stream)
+        rec = {"metric": "scanned text GB/s (% of HBM peak), batched vs plain", "value": b["value"],
+               "unit": "GB/s", "n_gpus": 1, "steps": max(3, args.steps // 2), "warmup": args.warmup,
+               "ms_per_step": b["graph_ms"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+               "config": {"workload": b["workload"], "n_texts": b["n_texts"], "n_bytes": b["text_bytes"],
+                          "automata": b["automata"], "kernel": "batch_scan"},
+               "pct_hbm_peak": round(100 * b["value"] / HBM_PEAK_GBS, 2), "roofline": b["roofline"],
+               "cpu_baseline": None, "batched": b}
+        print(json.dumps(rec), flush=True)
+        return
 
     log("generate", args.workload)
     w = plain_workload(args.workload)
@@ -177,6 +284,11 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_sample_mib << 20)
+    del copies, outs
+    batched = None
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        batched = bench_batched(args, torch, ac, stream)
 
     rec = {
         "metric": "scanned text GB/s (% of HBM peak)",
@@ -206,6 +318,7 @@ def main():
         "sort_ms": sort_ms,
         "pfac": pfac,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(rec), flush=True)
 

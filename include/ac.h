@@ -222,6 +222,76 @@ uint64_t ac_sort_scratch_bytes(uint64_t count);
 int ac_sort_matches(uint64_t *d_keys, uint64_t count, void *d_tmp, uint64_t tmp_bytes,
                     void *stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many texts against several resident automata in one persistent launch. The
+ * texts live in one device buffer (the "batch buffer"); text t occupies bytes
+ * [text_off[t], text_off[t] + text_len[t]) of it and is matched against
+ * automaton text_auto[t]. Matches are reported as
+ * (end position in the batch buffer << 32) | pattern id of that text's
+ * automaton, so the batch buffer must be shorter than 2^32 bytes. Each
+ * text's list equals what ac_scan reports for it alone, shifted by its offset.
+ */
+typedef struct ac_batch ac_batch;
+
+typedef struct {
+    uint32_t placement; /* AC_PLACE_AUTO (LDS_HOT when every automaton has an LDS
+                           image, else GLOBAL), AC_PLACE_LDS_HOT or AC_PLACE_GLOBAL */
+    uint32_t walkers;   /* chunks walked per lane (1, 2, 4); 0 = by placement */
+    uint32_t chunk;     /* end positions per work item; 0 = from the batch size */
+    uint32_t reserved;
+} ac_batch_tune;
+
+typedef struct {
+    uint32_t placement, walkers, block_bytes, chunk;
+    uint32_t threads;  /* per workgroup */
+    uint32_t grid;     /* workgroups of the persistent launch */
+    uint32_t n_items;  /* work items (chunks of texts) */
+    uint32_t n_tasks;  /* runs of items of one automaton, split over the grid */
+    uint64_t text_bytes;
+} ac_batch_info_t;
+
+/*
+ * ac_batch_create -- plan a batch: cut every text into work items, order them
+ * by automaton, upload the plan (on `stream`, synchronised before return).
+ *
+ *   autos, n_autos    automata built with ac_build on the current device, all
+ *                     with the same byte-class scheme (ac_info: class_hashed and
+ *                     n_cols); for AC_PLACE_LDS_HOT build them with
+ *                     placement AC_PLACE_LDS_HOT so each has an image
+ *   text_off          host, n_texts offsets into the batch buffer, multiples of 16
+ *   text_len          host, n_texts lengths (0 allowed)
+ *   text_auto         host, n_texts automaton indices
+ *   tune              NULL for defaults (see ac_batch_tune)
+ *   out               receives the plan; free with ac_batch_free
+ *
+ * The automata must outlive the plan. Errors: AC_ERR_INVALID (NULL arrays,
+ * misaligned offsets, an index past n_autos, mixed class schemes, a placement
+ * the automata cannot use), AC_ERR_TOO_LARGE (buffer of 2^32 bytes or more),
+ * AC_ERR_NOMEM, AC_ERR_HIP.
+ */
+int ac_batch_create(const ac_automaton *const *autos, uint32_t n_autos, const uint64_t *text_off,
+                    const uint64_t *text_len, const uint32_t *text_auto, uint32_t n_texts,
+                    const ac_batch_tune *tune, void *stream, ac_batch **out);
+
+/* ac_batch_info -- the plan's resolved choices and sizes. */
+int ac_batch_info(const ac_batch *b, ac_batch_info_t *info);
+
+/*
+ * ac_batch_scan -- reset *d_count and scan the whole batch in one launch on
+ * `stream` (asynchronous). d_texts: device batch buffer, 16-byte aligned,
+ * covering every text of the plan. With use_graph nonzero the reset and the
+ * launch are captured into a hipGraph on the first call (and again whenever
+ * the buffer arguments change) and replayed on `stream` afterwards.
+ * Overflow is reported as by ac_scan: *d_count holds the true total.
+ * The plan holds the launch's task counter, so scans of one plan must not
+ * overlap (issue them on one stream, or synchronise between streams).
+ */
+int ac_batch_scan(ac_batch *b, const uint8_t *d_texts, uint64_t *d_matches, uint64_t capacity,
+                  uint64_t *d_count, int use_graph, void *stream);
+
+/* ac_batch_free -- release the plan and its graph. NULL is a no-op. */
+void ac_batch_free(ac_batch *b);
+
 /* ac_last_error -- message of the last failing call on this thread ("" if none). */
 const char *ac_last_error(void);
 

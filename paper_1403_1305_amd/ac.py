@@ -66,6 +66,19 @@ class ac_scan_opts(ctypes.Structure):
                 ("walkers", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32)]
 
 
+class ac_batch_tune(ctypes.Structure):
+    _fields_ = [("placement", ctypes.c_uint32), ("walkers", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ac_batch_info_t(ctypes.Structure):
+    _fields_ = [("placement", ctypes.c_uint32), ("walkers", ctypes.c_uint32),
+                ("block_bytes", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("threads", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("n_items", ctypes.c_uint32), ("n_tasks", ctypes.c_uint32),
+                ("text_bytes", ctypes.c_uint64)]
+
+
 _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
@@ -86,6 +99,11 @@ SIGNATURES = {
                                       ctypes.POINTER(ac_scan_opts), _vp]),
     "ac_sort_scratch_bytes": (_u64, [_u64]),
     "ac_sort_matches": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp]),
+    "ac_batch_create": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, ctypes.POINTER(ac_batch_tune),
+                                       _vp, ctypes.POINTER(_vp)]),
+    "ac_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ac_batch_info_t)]),
+    "ac_batch_scan": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, ctypes.c_int, _vp]),
+    "ac_batch_free": (None, [_vp]),
     "ac_last_error": (ctypes.c_char_p, []),
 }
 
@@ -249,6 +267,67 @@ def ac_sort_scratch_bytes(count: int) -> int:
 def ac_sort_matches(d_keys, count: int, d_tmp, tmp_bytes: int, stream=None) -> None:
     _check(load_library().ac_sort_matches(_ptr(d_keys), count, _ptr(d_tmp), tmp_bytes,
                                           _stream(stream)))
+
+
+class Batch:
+    """Owning handle of an ac_batch* plan (keeps its automata alive)."""
+
+    def __init__(self, handle: int, autos):
+        self.handle = handle
+        self.autos = list(autos)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ac_batch_free(self.handle)
+            self.handle = None
+
+
+def ac_batch_create(autos, text_off, text_len, text_auto, tune: ac_batch_tune | None = None,
+                    stream=None) -> Batch:
+    lib = load_library()
+    arr = (ctypes.c_void_p * len(autos))(*[a.handle for a in autos])
+    off = np.ascontiguousarray(text_off, dtype=np.uint64)
+    ln = np.ascontiguousarray(text_len, dtype=np.uint64)
+    au = np.ascontiguousarray(text_auto, dtype=np.uint32)
+    h = _vp()
+    _check(lib.ac_batch_create(arr, len(autos), off.ctypes.data, ln.ctypes.data, au.ctypes.data,
+                               len(off), ctypes.byref(tune) if tune is not None else None,
+                               _stream(stream), ctypes.byref(h)))
+    return Batch(h.value, autos)
+
+
+def ac_batch_info(b: Batch) -> dict:
+    info = ac_batch_info_t()
+    _check(load_library().ac_batch_info(b.handle, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in ac_batch_info_t._fields_}
+
+
+def ac_batch_scan(b: Batch, d_texts, d_matches, capacity: int, d_count, use_graph: bool = False,
+                  stream=None) -> None:
+    _check(load_library().ac_batch_scan(b.handle, _ptr(d_texts), _ptr(d_matches), capacity,
+                                        _ptr(d_count), int(bool(use_graph)), _stream(stream)))
+
+
+def ac_batch_free(b: Batch) -> None:
+    if b.handle:
+        load_library().ac_batch_free(b.handle)
+        b.handle = None
+
+
+def pack_texts(texts, align: int = 16) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Concatenate host texts into one buffer, each starting at a multiple of
+    `align`; returns (buffer uint8, offsets uint64, lengths uint64)."""
+    lens = np.array([len(t) for t in texts], dtype=np.uint64)
+    offs = np.zeros(len(texts), dtype=np.uint64)
+    pos = 0
+    for i, t in enumerate(texts):
+        offs[i] = pos
+        pos += (len(t) + align - 1) // align * align
+    buf = np.zeros(max(align, pos), dtype=np.uint8)
+    for i, t in enumerate(texts):
+        buf[int(offs[i]):int(offs[i]) + len(t)] = np.frombuffer(bytes(t), dtype=np.uint8) \
+            if isinstance(t, (bytes, bytearray)) else t
+    return buf, offs, lens
 
 
 def ac_last_error() -> str:

@@ -6,27 +6,23 @@
 #include <string>
 
 #include "../../include/ac.h"
+#include "automaton.h"
 #include "device_common.h"
 #include "machine.h"
 #include "scan.h"
 
-struct ac_automaton {
-    acm::Machine m;
-    acm::DeviceMachine dm;
-    bool on_device = false;
-    int device = -1;
-    uint32_t placement = AC_PLACE_GLOBAL;  // resolved default for scans
-    std::vector<void *> allocations;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const std::string &msg) {
+int acm::set_error(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
+
+namespace {
+
+int fail(int code, const std::string &msg) { return acm::set_error(code, msg); }
 
 // Largest LDS image, in bytes, a build may plan for: the LDS of a workgroup
 // less the match queues of 16 waves and some slack.

@@ -101,16 +101,19 @@ inline int hip_fail(hipError_t e, const char *what, std::string &err) {
     return AC_ERR_HIP;
 }
 
-// Launch with `lds` bytes of dynamic LDS (raising the per-kernel limit when
-// above 64 KiB) and report launch errors.
+// Raise `kernel`'s dynamic-LDS limit to at least `lds` bytes on the current
+// device (a no-op up to 64 KiB, and once granted; defined in scan.hip).
+hipError_t allow_lds(const void *kernel, uint32_t lds);
+// Workgroups of `block` threads and `lds` bytes that one CU holds at once
+// (at least 1), cached per device, kernel and shape.
+int occupancy(const void *kernel, uint32_t block, uint32_t lds);
+
+// Launch with `lds` bytes of dynamic LDS and report launch errors.
 template <typename K, typename A>
 int launch_kernel(K kernel, uint32_t grid, uint32_t block, uint32_t lds, hipStream_t stream,
                   const A &args, std::string &err) {
-    if (lds > 64u * 1024u) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute", err);
-    }
+    hipError_t le = allow_lds(reinterpret_cast<const void *>(kernel), lds);
+    if (le != hipSuccess) return hip_fail(le, "hipFuncSetAttribute", err);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, args);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch", err);

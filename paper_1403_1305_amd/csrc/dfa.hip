@@ -34,21 +34,7 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
     dfa::DfaArgs a{};
     a.text = text;
     a.n = uint32_t(n);
-    a.back = dm.m_max - 1;
-    a.n_cols = dm.n_cols;
-    a.hot = dm.hot_states;
-    a.acc_end = dm.acc_end;
-    a.table_words = dm.n_states * dm.n_cols;
-    a.hash_shift = dm.hash_shift;
-    a.letters_lo = uint32_t(dm.hash_letter[0]) | uint32_t(dm.hash_letter[1]) << 8 |
-                   uint32_t(dm.hash_letter[2]) << 16 | uint32_t(dm.hash_letter[3]) << 24;
-    a.letters_hi = uint32_t(dm.hash_letter[4]) | uint32_t(dm.hash_letter[5]) << 8 |
-                   uint32_t(dm.hash_letter[6]) << 16 | uint32_t(dm.hash_letter[7]) << 24;
-    a.dfa = dm.dfa;
-    a.hot_rows = dm.hot_dfa;
-    a.cmap = dm.cmap;
-    a.out_off = dm.out_off;
-    a.out_ids = dm.out_ids;
+    dfa::fill_machine_args(dm, a);
     a.out = out;
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long *>(count);
@@ -92,17 +78,8 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
         err = "ac_scan: no kernel for this placement / walker count";
         return AC_ERR_INVALID;
     }
-    if (lds > 64u * 1024u) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute", err);
-    }
     // resident workgroups per CU, as registers and LDS allow
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, int(block), size_t(lds)) != hipSuccess ||
-        occ <= 0)
-        occ = 1;
-    const uint32_t wg_per_cu = uint32_t(occ);
+    const uint32_t wg_per_cu = uint32_t(occupancy(reinterpret_cast<const void *>(kernel), block, lds));
     uint64_t chunk = cfg.chunk;
     if (chunk == 0) {
         // enough walkers for every lane the chip holds, but chunks of at least

@@ -1,0 +1,13 @@
+// dfa_batch_hot.hip -- batch kernels with the 16-bit LDS image (own
+// translation unit so the instantiations compile in parallel).
+#include "dfa_kernel.h"
+
+namespace acm {
+namespace dfa {
+
+BatchKernel select_batch_hot(bool hashed, int l2, uint32_t K, uint32_t block_bytes) {
+    return select_batch_for<AC_PLACE_LDS_HOT>(hashed, l2, K, block_bytes);
+}
+
+}  // namespace dfa
+}  // namespace acm

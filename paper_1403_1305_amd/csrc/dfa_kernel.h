@@ -295,23 +295,12 @@ struct Walkers {
     }
 };
 
-// Text is read per walker in blocks of G 16-byte groups (64 or 128 bytes: a
-// half or a whole cache line, loaded back to back). With NBUF = 2 two register
-// buffers are used in turn, so one block is in flight while the other is
-// walked; with NBUF = 1 the next block is requested as soon as a block is
-// finished (fewer registers, and whole lines are never fetched twice).
-template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
-__global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
-    constexpr uint32_t BB = 16u * G;  // bytes per block
-    // LDS: per-wave match queues | byte map (256 B) | table image
-    extern __shared__ __align__(16) uint8_t smem[];
-    constexpr uint32_t kQueues = (BLOCK / 64) * kQueueBytesPerWave;
-    uint8_t *s_cmap = smem + kQueues;
-    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + kQueues + 256);
-    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + kQueues + 256);
+// The byte map and, for the LDS placements, the table image of `a` into LDS.
+// Every thread of the workgroup takes part; ends with a barrier.
+template <int PLACE, int BLOCK>
+__device__ __forceinline__ void load_tables(const DfaArgs &a, uint8_t *s_cmap, uint32_t *s_tab,
+                                            uint16_t *s_hot) {
     const uint32_t tid = threadIdx.x;
-    Emitter em;
-    em.init(smem, a.out, a.cap, a.count);
     for (uint32_t i = tid; i < 64; i += BLOCK)
         reinterpret_cast<uint32_t *>(s_cmap)[i] = reinterpret_cast<const uint32_t *>(a.cmap)[i];
     if constexpr (PLACE == AC_PLACE_LDS_FULL) {
@@ -322,6 +311,86 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
         for (uint32_t i = tid; i < words; i += BLOCK) reinterpret_cast<uint32_t *>(s_hot)[i] = src[i];
     }
     __syncthreads();
+}
+
+// Text is read per walker in blocks of G 16-byte groups (64 or 128 bytes: a
+// half or a whole cache line, loaded back to back). With NBUF = 2 two register
+// buffers are used in turn, so one block is in flight while the other is
+// walked; with NBUF = 1 the next block is requested as soon as a block is
+// finished (fewer registers, and whole lines are never fetched twice).
+//
+// Walker k owns end positions [own[k], hi[k]) and walks [wstart[k], hi[k])
+// (wstart a multiple of 16) from state s[k]; a walker without a chunk has
+// own = hi = wstart = 0 and walks nothing. On return s[k] is the state after
+// byte hi[k] - 1.
+template <int PLACE, int K, int LOG2C, bool HASHED, int NBUF, int G>
+__device__ __forceinline__ void walk_chunks(const Walkers<PLACE, K, LOG2C, HASHED> &W, const DfaArgs &a,
+                                            Emitter &em, const uint8_t *s_cmap, const uint32_t *s_tab,
+                                            const uint16_t *s_hot, uint32_t (&s_io)[K],
+                                            const uint32_t (&own_in)[K], const uint32_t (&hi_in)[K],
+                                            const uint32_t (&wstart_in)[K]) {
+    constexpr uint32_t BB = 16u * G;  // bytes per block
+    // Local copies: the compiler simplifies this function before inlining it,
+    // and walking through the callers' arrays then costs enough registers to
+    // spill the hashed two-walker kernels.
+    uint32_t s[K], own[K], hi[K], wstart[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        s[k] = s_io[k];
+        own[k] = own_in[k];
+        hi[k] = hi_in[k];
+        wstart[k] = wstart_in[k];
+    }
+    uint32_t bpos[K], bend[K];
+    TextBlock<G> A[K], B[NBUF == 2 ? K : 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        bpos[k] = wstart[k] & ~(BB - 1);
+        bend[k] = hi[k] & ~(BB - 1);
+        load_block(A[k], a.text, bpos[k], bpos[k] < bend[k]);
+        if constexpr (NBUF == 2)
+            load_block(B[k], a.text, bpos[k] + BB, bend[k] > BB && bpos[k] < bend[k] - BB);
+    }
+    while (true) {
+        bool any_left = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any_left |= bpos[k] < bend[k];
+        if (!__any(any_left)) break;
+        W.block(A, s, own, wstart, bpos, bend, NBUF * BB);
+        if constexpr (NBUF == 2) {
+            any_left = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) any_left |= bpos[k] < bend[k];
+            if (!__any(any_left)) break;
+            W.block(B, s, own, wstart, bpos, bend, 2 * BB);
+        }
+    }
+    // bytes past the last full block (chunks whose end is not block-aligned),
+    // or the whole walk when the chunk has no full block
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        for (uint32_t p = max(bend[k], wstart[k]); p < hi[k]; ++p) {
+            const uint32_t e = step_byte<PLACE, LOG2C>(s[k], a.text[p], a, s_cmap, s_tab, s_hot);
+            s[k] = e & kStateMask;
+            emit_set(em, (e & kAccept) && p >= own[k], s[k], a.base + p, a.out_off, a.out_ids);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) s_io[k] = s[k];
+}
+
+template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
+__global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
+    // LDS: per-wave match queues | byte map (256 B) | table image
+    extern __shared__ __align__(16) uint8_t smem[];
+    constexpr uint32_t kQueues = (BLOCK / 64) * kQueueBytesPerWave;
+    uint8_t *s_cmap = smem + kQueues;
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + kQueues + 256);
+    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + kQueues + 256);
+    const uint32_t tid = threadIdx.x;
+    Emitter em;
+    em.init(smem, a.out, a.cap, a.count);
+    load_tables<PLACE, BLOCK>(a, s_cmap, s_tab, s_hot);
 
     const Walkers<PLACE, K, LOG2C, HASHED> W{a, s_cmap, s_tab, s_hot, em};
     const uint32_t lanes = gridDim.x * BLOCK;
@@ -331,8 +400,7 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
         // walker k: chunk `base + k * lanes + lane`, owning [own, hi); it walks
         // [wstart, hi) with wstart = own - m_max + 1 rounded down to 16 bytes
         // (starting earlier than needed only repeats warm-up steps).
-        uint32_t s[K], own[K], hi[K], wstart[K], bpos[K], bend[K];
-        TextBlock<G> A[K], B[NBUF == 2 ? K : 1];
+        uint32_t s[K], own[K], hi[K], wstart[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t ch = base + k * lanes + lane;
@@ -340,46 +408,121 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
             own[k] = act ? ch * a.chunk : 0u;
             hi[k] = act ? uint32_t(min(uint64_t(own[k]) + a.chunk, uint64_t(a.n))) : 0u;
             wstart[k] = (own[k] > a.back ? own[k] - a.back : 0u) & ~15u;
-            bpos[k] = wstart[k] & ~(BB - 1);
-            bend[k] = hi[k] & ~(BB - 1);
             // a walk that would start before byte 0 starts there instead, in the
             // state the text's earlier pieces ended in (the root for a new text)
             s[k] = (act && own[k] <= a.back && a.state_in) ? *a.state_in : 0u;
-            load_block(A[k], a.text, bpos[k], bpos[k] < bend[k]);
-            if constexpr (NBUF == 2)
-                load_block(B[k], a.text, bpos[k] + BB, bend[k] > BB && bpos[k] < bend[k] - BB);
         }
-        while (true) {
-            bool any_left = false;
+        walk_chunks<PLACE, K, LOG2C, HASHED, NBUF, G>(W, a, em, s_cmap, s_tab, s_hot, s, own, hi, wstart);
+        // the last chunk's walker ends exactly in the text's final state: it
+        // walked at least m_max bytes or started from the carried state
 #pragma unroll
-            for (int k = 0; k < K; ++k) any_left |= bpos[k] < bend[k];
-            if (!__any(any_left)) break;
-            W.block(A, s, own, wstart, bpos, bend, NBUF * BB);
-            if constexpr (NBUF == 2) {
-                any_left = false;
-#pragma unroll
-                for (int k = 0; k < K; ++k) any_left |= bpos[k] < bend[k];
-                if (!__any(any_left)) break;
-                W.block(B, s, own, wstart, bpos, bend, 2 * BB);
-            }
-        }
-        // bytes past the last full block (chunks whose end is not block-aligned),
-        // or the whole walk when the chunk has no full block
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (base + k * lanes + lane < a.n_chunks) {
-                for (uint32_t p = max(bend[k], wstart[k]); p < hi[k]; ++p) {
-                    const uint32_t e = step_byte<PLACE, LOG2C>(s[k], a.text[p], a, s_cmap, s_tab, s_hot);
-                    s[k] = e & kStateMask;
-                    emit_set(em, (e & kAccept) && p >= own[k], s[k], a.base + p, a.out_off, a.out_ids);
-                }
-                // the last chunk's walker ends exactly in the text's final state:
-                // it walked at least m_max bytes or started from the carried state
-                if (base + k * lanes + lane == a.n_chunks - 1 && a.state_out) *a.state_out = s[k];
-            }
-        }
+        for (int k = 0; k < K; ++k)
+            if (base + k * lanes + lane == a.n_chunks - 1 && a.state_out) *a.state_out = s[k];
     }
     em.flush();
+}
+
+// ------------------------------------------------------------------ batches
+// Many texts in one buffer, each with its own automaton. The host cuts every
+// text into work items (chunks) and groups the items of one automaton into
+// tasks of at most one item per walker. Workgroups take tasks from a shared
+// counter, so tasks are handed out in increasing order: a workgroup meets the
+// automata in order and reloads its LDS image at most once per automaton,
+// while fast and slow automata still balance across the grid.
+struct BatchItem {
+    uint32_t own_lo, own_hi;  // end positions this item reports, in the batch buffer
+    uint32_t text_lo;         // first byte of its text (a multiple of 16)
+    uint32_t pad;
+};
+struct BatchTask {
+    uint32_t item_begin, item_end;  // items [item_begin, item_end) of one automaton,
+                                    // at most one per walker of a workgroup
+    uint32_t automaton;
+    uint32_t pad;
+};
+struct BatchArgs {
+    const uint8_t *text;
+    const BatchItem *items;
+    const BatchTask *tasks;
+    uint32_t n_tasks;
+    const DfaArgs *autos;  // per automaton: tables, sizes and class scheme
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+    uint32_t *next_task;   // task counter, zero at launch
+};
+
+template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
+__global__ void __launch_bounds__(BLOCK) batch_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    constexpr uint32_t kQueues = (BLOCK / 64) * kQueueBytesPerWave;
+    uint8_t *s_cmap = smem + kQueues;
+    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + kQueues + 256);
+    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + kQueues + 256);
+    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t s_task;
+    Emitter em;
+    em.init(smem, b.out, b.cap, b.count);
+    uint32_t loaded = 0xffffffffu;
+    while (true) {
+        // the first barrier also ends every thread's previous task, so the
+        // LDS image may be replaced below; the second lets thread 0 reuse s_task
+        if (tid == 0) s_task = atomicAdd(b.next_task, 1u);
+        __syncthreads();
+        // uniform across the workgroup: keeps the task and its automaton's
+        // arguments in scalar registers
+        const uint32_t t = __builtin_amdgcn_readfirstlane(s_task);
+        __syncthreads();
+        if (t >= b.n_tasks) break;
+        const BatchTask task = b.tasks[t];
+        DfaArgs a = b.autos[task.automaton];
+        a.text = b.text;
+        a.out = b.out;
+        a.cap = b.cap;
+        a.count = b.count;
+        a.base = 0;
+        a.state_in = nullptr;
+        a.state_out = nullptr;
+        if (task.automaton != loaded) {
+            load_tables<PLACE, BLOCK>(a, s_cmap, s_tab, s_hot);
+            loaded = task.automaton;
+        }
+        const Walkers<PLACE, K, LOG2C, HASHED> W{a, s_cmap, s_tab, s_hot, em};
+        // a task holds at most one item per walker (K x BLOCK)
+        uint32_t s[K], own[K], hi[K], wstart[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t i = task.item_begin + k * BLOCK + tid;
+            const BatchItem it = i < task.item_end ? b.items[i] : BatchItem{0, 0, 0, 0};
+            own[k] = it.own_lo;
+            hi[k] = it.own_hi;
+            // the walk never starts before its own text
+            wstart[k] = (own[k] - it.text_lo > a.back ? own[k] - a.back : it.text_lo) & ~15u;
+            s[k] = 0;
+        }
+        walk_chunks<PLACE, K, LOG2C, HASHED, NBUF, G>(W, a, em, s_cmap, s_tab, s_hot, s, own, hi, wstart);
+    }
+    em.flush();
+}
+
+// Table pointers, sizes and class scheme of a machine (the text, output and
+// chunking fields are left for the caller).
+inline void fill_machine_args(const DeviceMachine &dm, DfaArgs &a) {
+    a.back = dm.m_max - 1;
+    a.n_cols = dm.n_cols;
+    a.hot = dm.hot_states;
+    a.acc_end = dm.acc_end;
+    a.table_words = dm.n_states * dm.n_cols;
+    a.hash_shift = dm.hash_shift;
+    a.letters_lo = uint32_t(dm.hash_letter[0]) | uint32_t(dm.hash_letter[1]) << 8 |
+                   uint32_t(dm.hash_letter[2]) << 16 | uint32_t(dm.hash_letter[3]) << 24;
+    a.letters_hi = uint32_t(dm.hash_letter[4]) | uint32_t(dm.hash_letter[5]) << 8 |
+                   uint32_t(dm.hash_letter[6]) << 16 | uint32_t(dm.hash_letter[7]) << 24;
+    a.dfa = dm.dfa;
+    a.hot_rows = dm.hot_dfa;
+    a.cmap = dm.cmap;
+    a.out_off = dm.out_off;
+    a.out_ids = dm.out_ids;
 }
 
 using DfaKernel = void (*)(DfaArgs);
@@ -411,6 +554,35 @@ DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) 
 #undef AC_DFA_V
     return nullptr;
 }
+
+using BatchKernel = void (*)(BatchArgs);
+
+// Batch kernel for a placement (LDS_HOT or GLOBAL), walker count, block size
+// and class scheme (shared by every automaton of the batch).
+template <int PLACE>
+BatchKernel select_batch_for(bool hashed, int l2, uint32_t K, uint32_t block_bytes) {
+    constexpr bool kHot = PLACE == AC_PLACE_LDS_HOT;
+#define AC_B_V(KK, LL, HH, NB, GG)                                                                  \
+    return batch_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
+#define AC_B_CASE(KK, LL, HH)                                                                       \
+    if (K == KK && l2 == LL && hashed == HH) {                                                      \
+        if constexpr (KK == 4) { AC_B_V(KK, LL, HH, 1, 4) }                                         \
+        else { AC_B_V(KK, LL, HH, 1, 8) }                                                           \
+    }
+#define AC_B_KS(LL, HH) AC_B_CASE(1, LL, HH) AC_B_CASE(2, LL, HH) AC_B_CASE(4, LL, HH)
+    AC_B_KS(-1, false)
+    AC_B_KS(0, true)
+    AC_B_KS(1, true)
+    AC_B_KS(2, true)
+    AC_B_KS(3, true)
+#undef AC_B_KS
+#undef AC_B_CASE
+#undef AC_B_V
+    return nullptr;
+}
+
+BatchKernel select_batch_hot(bool hashed, int l2, uint32_t K, uint32_t block_bytes);
+BatchKernel select_batch_global(bool hashed, int l2, uint32_t K, uint32_t block_bytes);
 
 DfaKernel select_global(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 DfaKernel select_full(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);

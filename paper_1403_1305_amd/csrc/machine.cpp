@@ -252,8 +252,8 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
                         ++extra;
                     }
                 }
-        if (image && H < kMinHotStates && H < want) {
-            image = false;  // too few rows left to be worth an LDS image
+        if (image && H < kMinHotStates && H < cand.size()) {
+            image = false;  // shrunk to too few rows to be worth an LDS image
             H = 1;
             continue;
         }

@@ -4,7 +4,10 @@
 #include "scan.h"
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/ac.h"
@@ -196,6 +199,40 @@ __global__ void __launch_bounds__(kSortBlock) sort_scatter_kernel(const uint64_t
 }
 
 }  // namespace
+
+hipError_t allow_lds(const void *kernel, uint32_t lds) {
+    if (lds <= 64u * 1024u) return hipSuccess;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, uint32_t> granted;
+    std::lock_guard<std::mutex> g(mu);
+    uint32_t &have = granted[{dev, kernel}];
+    if (have >= lds) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e == hipSuccess) have = lds;
+    return e;
+}
+
+int occupancy(const void *kernel, uint32_t block, uint32_t lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, uint32_t, uint32_t>, int> known;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = known.find({dev, kernel, block, lds});
+        if (it != known.end()) return it->second;
+    }
+    int occ = 0;
+    if (allow_lds(kernel, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, int(block), size_t(lds)) != hipSuccess ||
+        occ <= 0)
+        occ = 1;
+    std::lock_guard<std::mutex> g(mu);
+    known[{dev, kernel, block, lds}] = occ;
+    return occ;
+}
 
 int compute_units(int device) {
     static std::mutex mu;

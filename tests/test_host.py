@@ -219,3 +219,15 @@ def test_large_protein_set_builds():
     # forcing the hot placement keeps whatever image fits
     t2 = Tables(build_host(w.patterns, placement=ac.AC_PLACE_LDS_HOT))
     assert np.array_equal(t2.dfa_walk(text), oracle.oracle_match(text, w.patterns))
+
+
+def test_small_machine_image_is_complete():
+    """A machine whose non-final states all fit the LDS image keeps that
+    image (every non-final state hot) when LDS_HOT is asked for."""
+    for pats in ([b"AB", b"ABG", b"BEDE", b"EF"], [b"ACG", b"T"],
+                 [bytes(p) for p in plain_workload("dna1m", n=1 << 12).patterns[:7]]):
+        t = Tables(build_host(pats, placement=ac.AC_PLACE_LDS_HOT))
+        accept = np.diff(t.out_off.astype(np.int64)) > 0
+        assert t.info["hot_states"] == int((~accept).sum()), pats
+        assert t.info["placement"] == ac.AC_PLACE_LDS_HOT
+        check_invariants(t, pats)
