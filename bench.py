@@ -182,13 +182,117 @@ def bench_batched(args, torch, ac, stream):
     }
 
 
+SERVED_DESC = ("scan requests with lengths log-uniform in [1 KiB, 64 MiB], half DNA and half skewed protein; "
+               "8 resident automata of 1,000-50,000 patterns (4 DNA, lengths 8-32; 4 protein, 6-20); "
+               "Poisson arrivals at a fixed rate; HBM-budget admission")
+
+
+def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
+    """The served form: requests replayed through ac_serve_* (continuous
+    batching, budget admission, pieces with carried state) against the same
+    requests as serial plain ac_scan launches on one stream."""
+    import numpy as np
+
+    from synth import served_workload
+
+    log("generate served")
+    w = served_workload()
+    R = len(w.length)
+    total = int(w.length.sum())
+    d_texts = [torch.from_numpy(t).to("cuda") for t in w.texts]
+    t0 = time.perf_counter()
+    autos = []
+    for s in w.sets:
+        d, o = ac.patterns_csr(s)
+        autos.append(ac.ac_build(d, o))
+    build_s = time.perf_counter() - t0
+    views = [d_texts[int(w.alpha[i])][int(w.offset[i]):int(w.offset[i] + w.length[i])] for i in range(R)]
+
+    # serial plain scans: one after another on one stream
+    cap = 1 << 26
+    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    counts = torch.zeros(R, dtype=torch.int64, device="cuda")
+
+    def serial(_):
+        for i in range(R):
+            ac.ac_scan(autos[int(w.automaton[i])], views[i], int(w.length[i]), out, cap, counts[i:i + 1],
+                       None, stream)
+
+    serial(0)
+    torch.cuda.synchronize()
+    swall, sms = time_steps(serial, 2, stream, torch)
+    plain_counts = counts.cpu().numpy()
+    serial_gbs = total * len(sms) / swall / 1e9
+    serial_ms = swall / len(sms) * 1e3
+    del out
+    torch.cuda.empty_cache()
+
+    budget = 4 << 30
+    srv = ac.Server(autos, hbm_budget=budget, max_inflight=8)
+
+    def replay(arrivals_ns):
+        base = srv.now_ns() + 50_000_000  # submissions finish well before the first arrival
+        tickets = [srv.submit(int(w.automaton[i]), views[i], n=int(w.length[i]), on_device=True,
+                              arrival_ns=base + int(arrivals_ns[i])) for i in range(R)]
+        res = []
+        for t in tickets:
+            r = srv.wait(t)
+            res.append((r.t_submit_ns, r.t_admit_ns, r.t_done_ns, r.n_matches, r.rescans))
+            srv.release(t)
+        a = np.array(res, dtype=np.float64)
+        lat = (a[:, 2] - a[:, 0]) / 1e6
+        span = (a[:, 2].max() - a[:, 0].min()) / 1e9
+        return {"value": round(total / span / 1e9, 3), "unit": "GB/s",
+                "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                "mean_ms": round(float(lat.mean()), 4), "makespan_ms": round(span * 1e3, 3),
+                "rescans": int(a[:, 4].sum())}, a[:, 3].astype(np.int64)
+
+    log("served: saturated")
+    replay(np.zeros(R))  # warm-up: rates learnt, kernels loaded
+    sat, got = replay(np.zeros(R))
+    exact = bool(np.array_equal(got, plain_counts))
+    sat["running_peak"] = srv.stats()["running_peak"]
+    rng = np.random.default_rng(6)
+    poisson = []
+    for rho in rhos:
+        lam = rho * serial_gbs * 1e9 / (total / R)  # requests per second
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=R)) * 1e9
+        arr -= arr[0]
+        log(f"served: poisson rho={rho}")
+        rec, got = replay(arr)
+        exact &= bool(np.array_equal(got, plain_counts))
+        rec.update({"rho": rho, "rate_per_s": round(lam, 1)})
+        poisson.append(rec)
+
+    # full lists of a sample of requests: served vs plain
+    sample = np.argsort(w.length)[:: max(1, R // 12)]
+    for i in sample:
+        t = srv.submit(int(w.automaton[i]), views[i], n=int(w.length[i]), on_device=True)
+        r = srv.wait(t)
+        a = np.sort(srv.keys(r))
+        srv.release(t)
+        b = np.sort(ac.keys_to_numpy(ac.scan_text(autos[int(w.automaton[i])], views[i])))
+        exact &= bool(np.array_equal(a, b))
+    st = srv.stats()
+    srv.close()
+    return {
+        "workload": f"served: {SERVED_DESC}", "requests": R, "text_bytes": total, "automata": len(autos),
+        "slots": 8, "hbm_budget": budget, "piece_bytes": 16 << 20,
+        "serial_plain": {"value": round(serial_gbs, 3), "unit": "GB/s", "ms": round(serial_ms, 3)},
+        "saturated": sat, "poisson": poisson,
+        "exact_vs_plain": exact, "pool_peak": st["pool_peak"], "build_s": round(build_s, 2),
+    }
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched"])
+    p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched", "served"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched sub-benchmark")
+    p.add_argument("--no-served", action="store_true", help="skip the served sub-benchmark")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)
@@ -224,6 +328,20 @@ def main():
                           "automata": b["automata"], "kernel": "batch_scan"},
                "pct_hbm_peak": round(100 * b["value"] / HBM_PEAK_GBS, 2), "roofline": b["roofline"],
                "cpu_baseline": None, "batched": b}
+        print(json.dumps(rec), flush=True)
+        return
+
+    if args.workload == "served":
+        v = bench_served(args, torch, ac, stream)
+        p80 = v["poisson"][-1]
+        rec = {"metric": "served aggregate GB/s (saturated) with p50/p99 latency under Poisson load",
+               "value": v["saturated"]["value"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+               "ms_per_step": v["saturated"]["makespan_ms"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+               "config": {"workload": v["workload"], "requests": v["requests"], "n_bytes": v["text_bytes"],
+                          "automata": v["automata"], "kernel": "dfa_scan (served)"},
+               "p50_ms": p80["p50_ms"], "p99_ms": p80["p99_ms"], "roofline": None, "cpu_baseline": None,
+               "served": v}
         print(json.dumps(rec), flush=True)
         return
 
@@ -289,6 +407,10 @@ def main():
     if not args.no_batched:
         torch.cuda.empty_cache()
         batched = bench_batched(args, torch, ac, stream)
+    served = None
+    if not args.no_served:
+        torch.cuda.empty_cache()
+        served = bench_served(args, torch, ac, stream)
 
     rec = {
         "metric": "scanned text GB/s (% of HBM peak)",
@@ -319,6 +441,7 @@ def main():
         "pfac": pfac,
         "cpu_baseline": cpu,
         "batched": batched,
+        "served": served,
     }
     print(json.dumps(rec), flush=True)
 

@@ -292,6 +292,95 @@ int ac_batch_scan(ac_batch *b, const uint8_t *d_texts, uint64_t *d_matches, uint
 /* ac_batch_free -- release the plan and its graph. NULL is a no-op. */
 void ac_batch_free(ac_batch *b);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop over resident automata with continuous batching: requests
+ * are admitted while others are on the device, as slots (HIP streams) and a
+ * device-memory budget allow, and their scans overlap on the GPU. Each
+ * request is scanned in pieces with the DFA state carried on the device from
+ * one piece to the next (the per-buffer search of the paper's Alg. 1), and
+ * its match list equals what ac_scan reports for the same text alone.
+ */
+typedef struct ac_server ac_server;
+
+typedef struct {
+    uint64_t hbm_budget;   /* device bytes for request text copies and match lists
+                              (one allocation at create); 0 = 4 GiB */
+    uint32_t max_inflight; /* requests on the device at once (slots, <= 64); 0 = 8 */
+    uint32_t piece_bytes;  /* scan piece length, a multiple of 16; 0 = 16 MiB */
+    uint32_t match_ppm;    /* first guess of matches per million text bytes, used to
+                              size match lists until finished requests refine it;
+                              0 = 20000. A low guess costs a rescan, never a result. */
+    uint32_t reserved;
+} ac_serve_opts;
+
+typedef struct {
+    int32_t status;           /* AC_OK or the error that ended the request */
+    uint32_t automaton;
+    uint64_t n;               /* text bytes */
+    const uint64_t *d_matches; /* device keys (end << 32 | id, end relative to the
+                                  request's text), unordered; valid until
+                                  ac_serve_release */
+    uint64_t n_matches;
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* arrival, admission and completion,
+                                                    on the server's clock */
+    uint32_t pieces;          /* scan pieces */
+    uint32_t rescans;         /* scans repeated because the list was too small */
+} ac_serve_result;
+
+typedef struct {
+    uint64_t submitted, completed, failed, queued, running, rescans;
+    uint64_t pool_bytes, pool_used, pool_peak;
+    uint64_t running_peak;  /* most requests on the device at once */
+} ac_serve_stats_t;
+
+/*
+ * ac_serve_create -- start a server on the current device over n_autos
+ * automata built with ac_build (they must outlive the server). Allocates the
+ * device pool and the slots and starts the scheduler thread.
+ * Errors: AC_ERR_INVALID, AC_ERR_NOMEM (pool), AC_ERR_HIP.
+ */
+int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac_serve_opts *opts,
+                    ac_server **out);
+
+/*
+ * ac_serve_submit -- queue a scan of `text` (n bytes) with automaton
+ * `automaton`; returns at once with a ticket. arrival_ns = 0 means the request
+ * arrives now; a later time on the server's clock (ac_serve_now_ns) schedules
+ * its arrival, so that a recorded or generated arrival process can be
+ * replayed exactly: nothing is admitted before its arrival, and latency
+ * counts from it (t_submit_ns). With text_on_device nonzero the
+ * text is device memory (16-byte aligned) that must stay unchanged until the
+ * request is done; otherwise it is host memory that the server copies into
+ * its pool (use pinned memory for the copy to overlap other work), and that
+ * must stay valid until the request is done.
+ * Errors: AC_ERR_INVALID; AC_ERR_TOO_LARGE if n >= 2^32 or the request alone
+ * exceeds the budget.
+ */
+int ac_serve_submit(ac_server *s, uint32_t automaton, const uint8_t *text, uint64_t n, int text_on_device,
+                    uint64_t arrival_ns, uint64_t *ticket);
+
+/* ac_serve_now_ns -- the server's clock: nanoseconds since ac_serve_create. */
+uint64_t ac_serve_now_ns(const ac_server *s);
+
+/*
+ * ac_serve_wait -- block until the request is done (timeout_ms < 0: no limit)
+ * and describe it in *res. Returns AC_ERR_BUSY on timeout, the request's own
+ * error if it failed, else AC_OK. May be called again for the same ticket.
+ */
+int ac_serve_wait(ac_server *s, uint64_t ticket, int64_t timeout_ms, ac_serve_result *res);
+
+/* ac_serve_release -- give back a finished request's match list to the pool
+ * (a result not released keeps its bytes of the budget). */
+int ac_serve_release(ac_server *s, uint64_t ticket);
+
+/* ac_serve_stats -- counters and pool occupancy. */
+int ac_serve_stats(ac_server *s, ac_serve_stats_t *st);
+
+/* ac_serve_destroy -- finish what is on the device, fail what is still
+ * queued with AC_ERR_BUSY, stop the thread and free everything (unreleased
+ * match lists included). NULL is a no-op. */
+void ac_serve_destroy(ac_server *s);
+
 /* ac_last_error -- message of the last failing call on this thread ("" if none). */
 const char *ac_last_error(void);
 

@@ -79,6 +79,25 @@ class ac_batch_info_t(ctypes.Structure):
                 ("text_bytes", ctypes.c_uint64)]
 
 
+class ac_serve_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("piece_bytes", ctypes.c_uint32), ("match_ppm", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ac_serve_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("automaton", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("d_matches", ctypes.c_void_p), ("n_matches", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("pieces", ctypes.c_uint32), ("rescans", ctypes.c_uint32)]
+
+
+class ac_serve_stats_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "queued", "running",
+                                               "rescans", "pool_bytes", "pool_used", "pool_peak",
+                                               "running_peak")]
+
+
 _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
@@ -104,6 +123,13 @@ SIGNATURES = {
     "ac_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ac_batch_info_t)]),
     "ac_batch_scan": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, ctypes.c_int, _vp]),
     "ac_batch_free": (None, [_vp]),
+    "ac_serve_create": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(ac_serve_opts), ctypes.POINTER(_vp)]),
+    "ac_serve_submit": (ctypes.c_int, [_vp, _u32, _vp, _u64, ctypes.c_int, _u64, ctypes.POINTER(_u64)]),
+    "ac_serve_now_ns": (_u64, [_vp]),
+    "ac_serve_wait": (ctypes.c_int, [_vp, _u64, ctypes.c_int64, ctypes.POINTER(ac_serve_result)]),
+    "ac_serve_release": (ctypes.c_int, [_vp, _u64]),
+    "ac_serve_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ac_serve_stats_t)]),
+    "ac_serve_destroy": (None, [_vp]),
     "ac_last_error": (ctypes.c_char_p, []),
 }
 
@@ -312,6 +338,77 @@ def ac_batch_free(b: Batch) -> None:
     if b.handle:
         load_library().ac_batch_free(b.handle)
         b.handle = None
+
+
+class Server:
+    """Owning handle of an ac_server* (keeps its automata alive)."""
+
+    def __init__(self, autos, hbm_budget: int = 0, max_inflight: int = 0, piece_bytes: int = 0,
+                 match_ppm: int = 0):
+        lib = load_library()
+        self.autos = list(autos)
+        arr = (ctypes.c_void_p * len(self.autos))(*[a.handle for a in self.autos])
+        o = ac_serve_opts(hbm_budget, max_inflight, piece_bytes, match_ppm, 0)
+        h = _vp()
+        _check(lib.ac_serve_create(arr, len(self.autos), ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h.value
+
+    def submit(self, automaton: int, text, n: int | None = None, on_device: bool | None = None,
+               arrival_ns: int = 0) -> int:
+        """Queue a scan; `text` is a uint8 torch tensor (device or host) or a
+        numpy array (host); `arrival_ns` schedules its arrival on the server's
+        clock (0 = now). Returns the ticket."""
+        if isinstance(text, torch.Tensor):
+            n = text.numel() if n is None else n
+            on_device = text.is_cuda if on_device is None else on_device
+        elif isinstance(text, np.ndarray):
+            n = text.size if n is None else n
+            on_device = False
+        t = _u64()
+        _check(load_library().ac_serve_submit(self.handle, automaton, _ptr(text), n, int(bool(on_device)),
+                                              arrival_ns, ctypes.byref(t)))
+        return t.value
+
+    def now_ns(self) -> int:
+        return load_library().ac_serve_now_ns(self.handle)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> ac_serve_result:
+        r = ac_serve_result()
+        _check(load_library().ac_serve_wait(self.handle, ticket, timeout_ms, ctypes.byref(r)))
+        return r
+
+    @staticmethod
+    def keys_tensor(res: ac_serve_result) -> torch.Tensor:
+        """The request's match keys as an int64 device tensor that aliases the
+        server's list (bit pattern of the uint64 keys; valid until release)."""
+        n = int(res.n_matches)
+        if n == 0:
+            return torch.empty(0, dtype=torch.int64, device="cuda")
+
+        class _View:
+            __cuda_array_interface__ = {"shape": (n,), "typestr": "<i8", "data": (int(res.d_matches), False),
+                                        "version": 2, "strides": None}
+
+        return torch.as_tensor(_View(), device="cuda")
+
+    def keys(self, res: ac_serve_result) -> np.ndarray:
+        """The request's match keys copied to the host (unordered)."""
+        return keys_to_numpy(self.keys_tensor(res)).copy()
+
+    def release(self, ticket: int) -> None:
+        _check(load_library().ac_serve_release(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = ac_serve_stats_t()
+        _check(load_library().ac_serve_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ac_serve_stats_t._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ac_serve_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
 
 
 def pack_texts(texts, align: int = 16) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

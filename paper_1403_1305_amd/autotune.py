@@ -26,7 +26,7 @@ from . import ac
 
 CACHE_ENV = "AC_TUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1403_1305_amd", "batch_tune.json")
-CHUNKS = (0, 256, 512, 1024, 2048, 4096)  # 0 = the plan's own choice
+CHUNKS = (0, 128, 256, 512, 1024, 2048, 4096)  # 0 = the plan's own choice
 WALKERS = (1, 2, 4)
 
 

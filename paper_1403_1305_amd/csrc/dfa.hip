@@ -82,12 +82,17 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
     const uint32_t wg_per_cu = uint32_t(occupancy(reinterpret_cast<const void *>(kernel), block, lds));
     uint64_t chunk = cfg.chunk;
     if (chunk == 0) {
-        // enough walkers for every lane the chip holds, but chunks of at least
-        // 4 * m_max so that the re-walked overlap stays small
+        // One chunk per walker the chip holds. Where that leaves chunks of at
+        // least 4 * m_max (re-walked overlap under a quarter) they are rounded
+        // to whole text blocks. A shorter text cannot fill the chip at that
+        // length: its chunks stay short (down to 16 bytes) so that more lanes
+        // share it and each walk, which is latency-bound, is short.
         const uint64_t walkers = uint64_t(cus) * wg_per_cu * block * K;
-        chunk = (n + walkers - 1) / walkers;
-        chunk = std::max<uint64_t>(chunk, 4ull * dm.m_max);
-        chunk = std::max<uint64_t>(bb, (chunk + bb - 1) & ~uint64_t(bb - 1));
+        const uint64_t fill = (n + walkers - 1) / walkers;
+        if (fill >= 4ull * dm.m_max)
+            chunk = (fill + bb - 1) & ~uint64_t(bb - 1);
+        else
+            chunk = std::max<uint64_t>(16, (fill + 15) & ~uint64_t(15));
         chunk = std::min<uint64_t>(chunk, 1u << 30);
     }
     if (chunk % 16 != 0 || chunk == 0 || chunk > (1u << 30)) {

@@ -295,21 +295,38 @@ struct Walkers {
     }
 };
 
+// Copy `bytes` (a multiple of 4) from global memory to LDS, both 16-byte
+// aligned: 16-byte pieces with four loads in flight per thread before their
+// stores, then the last words.
+template <int BLOCK>
+__device__ __forceinline__ void copy_to_lds(void *dst, const void *src, uint32_t bytes) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n16 = bytes / 16;
+    const uint4 *s = reinterpret_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+    uint32_t i = tid;
+    for (; i + 3 * BLOCK < n16; i += 4 * BLOCK) {
+        const uint4 v0 = s[i], v1 = s[i + BLOCK], v2 = s[i + 2 * BLOCK], v3 = s[i + 3 * BLOCK];
+        d[i] = v0;
+        d[i + BLOCK] = v1;
+        d[i + 2 * BLOCK] = v2;
+        d[i + 3 * BLOCK] = v3;
+    }
+    for (; i < n16; i += BLOCK) d[i] = s[i];
+    for (uint32_t w = n16 * 4 + tid; w < bytes / 4; w += BLOCK)
+        static_cast<uint32_t *>(dst)[w] = static_cast<const uint32_t *>(src)[w];
+}
+
 // The byte map and, for the LDS placements, the table image of `a` into LDS.
 // Every thread of the workgroup takes part; ends with a barrier.
 template <int PLACE, int BLOCK>
 __device__ __forceinline__ void load_tables(const DfaArgs &a, uint8_t *s_cmap, uint32_t *s_tab,
                                             uint16_t *s_hot) {
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < 64; i += BLOCK)
-        reinterpret_cast<uint32_t *>(s_cmap)[i] = reinterpret_cast<const uint32_t *>(a.cmap)[i];
-    if constexpr (PLACE == AC_PLACE_LDS_FULL) {
-        for (uint32_t i = tid; i < a.table_words; i += BLOCK) s_tab[i] = a.dfa[i];
-    } else if constexpr (PLACE == AC_PLACE_LDS_HOT) {
-        const uint32_t words = (a.hot * a.n_cols + 1) / 2;  // image is padded to 4 bytes
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.hot_rows);
-        for (uint32_t i = tid; i < words; i += BLOCK) reinterpret_cast<uint32_t *>(s_hot)[i] = src[i];
-    }
+    copy_to_lds<BLOCK>(s_cmap, a.cmap, 256);
+    if constexpr (PLACE == AC_PLACE_LDS_FULL)
+        copy_to_lds<BLOCK>(s_tab, a.dfa, a.table_words * 4u);
+    else if constexpr (PLACE == AC_PLACE_LDS_HOT)
+        copy_to_lds<BLOCK>(s_hot, a.hot_rows, ((a.hot * a.n_cols + 1) / 2) * 4u);  // image padded to 4 bytes
     __syncthreads();
 }
 

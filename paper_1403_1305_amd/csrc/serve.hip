@@ -1,0 +1,594 @@
+// serve.hip -- the served form (the ac_serve_* entry points of include/ac.h).
+//
+// A scheduler thread admits scan requests into a fixed number of slots as
+// slots and device memory free up (continuous batching): each request holds
+// a slot (a HIP stream and a few device words) while it is on the device, and
+// bytes of one device pool for its text copy and its match list. Requests on
+// different slots overlap on the GPU. A request is scanned in pieces with the
+// DFA state carried on the device from piece to piece (the per-buffer search
+// of the paper's Alg. 1), so a long request never occupies the whole device
+// in one launch and host texts can be copied in while earlier pieces scan.
+//
+// The match list is sized before the count is known: the reservation is the
+// text length times a per-automaton match rate learnt from finished requests.
+// A request whose count exceeds its reservation is scanned again into a list
+// of the exact size (its text is still on the device), so results are exact
+// whatever the estimate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "automaton.h"
+#include "scan.h"
+
+namespace {
+
+using acm::set_error;
+using Clock = std::chrono::steady_clock;
+constexpr uint64_t kNone = ~0ull;
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kPieceEvents = 8;   // copy -> scan hand-off events per slot, reused in turn
+constexpr uint32_t kMaxBypass = 16;    // later requests admitted ahead of a waiting head, at most
+
+// First-fit allocator over one device allocation (offsets, 256-byte aligned).
+class DevicePool {
+public:
+    void init(uint64_t bytes) {
+        size_ = bytes;
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+        used_ = peak_ = 0;
+    }
+    uint64_t alloc(uint64_t bytes) {
+        bytes = std::max<uint64_t>(kAlign, (bytes + kAlign - 1) & ~(kAlign - 1));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const uint64_t off = it->first, rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            taken_[off] = bytes;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return off;
+        }
+        return kNone;
+    }
+    void release(uint64_t off) {
+        auto t = taken_.find(off);
+        if (t == taken_.end()) return;
+        uint64_t start = off, len = t->second;
+        used_ -= len;
+        taken_.erase(t);
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && start + len == next->first) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = len;
+    }
+    // Keep the first `bytes` of the block at `off` and free the rest.
+    void shrink(uint64_t off, uint64_t bytes) {
+        auto t = taken_.find(off);
+        if (t == taken_.end()) return;
+        bytes = std::max<uint64_t>(kAlign, (bytes + kAlign - 1) & ~(kAlign - 1));
+        if (bytes >= t->second) return;
+        uint64_t tail = off + bytes, len = t->second - bytes;
+        t->second = bytes;
+        used_ -= len;
+        auto next = free_.lower_bound(tail);
+        if (next != free_.end() && tail + len == next->first) {
+            len += next->second;
+            free_.erase(next);
+        }
+        free_[tail] = len;
+    }
+    uint64_t size() const { return size_; }
+    uint64_t used() const { return used_; }
+    uint64_t peak() const { return peak_; }
+
+private:
+    uint64_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<uint64_t, uint64_t> free_;   // offset -> length, coalesced
+    std::unordered_map<uint64_t, uint64_t> taken_;
+};
+
+enum class Phase { Queued, Running, WaitMemory, Done };
+
+struct Request {
+    uint64_t id = 0;
+    uint32_t automaton = 0;
+    const uint8_t *src = nullptr;
+    uint64_t n = 0;
+    bool on_device = false;
+    Phase phase = Phase::Queued;
+    int slot = -1;
+    uint64_t text_off = kNone, out_off = kNone, cap = 0;
+    const uint8_t *d_text = nullptr;
+    uint64_t *d_out = nullptr;
+    uint64_t n_matches = 0;
+    uint32_t pieces = 0, rescans = 0, bypassed = 0;
+    int status = AC_OK;
+    std::string message;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct Slot {
+    hipStream_t scan = nullptr, copy = nullptr;
+    hipEvent_t done = nullptr;
+    hipEvent_t piece[kPieceEvents] = {};
+    uint64_t *d_count = nullptr;  // device: match count
+    uint32_t *d_state = nullptr;  // device: two carried-state words, used in turn
+    uint64_t *h_count = nullptr;  // pinned host copy of the count
+    Request *req = nullptr;
+};
+
+}  // namespace
+
+struct ac_server {
+    int device = -1;
+    std::vector<const ac_automaton *> autos;
+    std::vector<double> rate;  // matches per text byte, per automaton
+    uint64_t piece = 0;
+    uint8_t *pool_base = nullptr;
+    DevicePool pool;
+    std::vector<Slot> slots;
+    void *words = nullptr;       // device words of every slot
+    uint64_t *h_counts = nullptr;  // pinned count words of every slot
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::vector<Request *> running;  // Running or WaitMemory
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+    uint64_t next_id = 1;
+    uint64_t submitted = 0, completed = 0, rescans = 0, failed = 0, running_peak = 0;
+    bool stop = false;
+    Clock::time_point t0;
+    std::thread worker;
+};
+
+namespace {
+
+uint64_t now_ns(const ac_server *s) {
+    return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - s->t0).count());
+}
+
+// Match-list keys reserved for a request: its length times the automaton's
+// learnt rate, with a quarter of headroom.
+uint64_t reservation(const ac_server *s, const Request *r) {
+    return uint64_t(double(r->n) * s->rate[r->automaton] * 1.25) + 1024;
+}
+
+void finish(ac_server *s, Request *r, int status, const std::string &msg) {
+    r->status = status;
+    r->message = msg;
+    r->phase = Phase::Done;
+    r->t_done = now_ns(s);
+    if (r->text_off != kNone) {
+        s->pool.release(r->text_off);
+        r->text_off = kNone;
+        r->d_text = r->on_device ? r->d_text : nullptr;
+    }
+    if (status != AC_OK && r->out_off != kNone) {
+        s->pool.release(r->out_off);
+        r->out_off = kNone;
+        r->d_out = nullptr;
+        ++s->failed;
+    }
+    if (r->slot >= 0) {
+        s->slots[size_t(r->slot)].req = nullptr;
+        r->slot = -1;
+    }
+    ++s->completed;
+    s->cv_done.notify_all();
+}
+
+// Queue the request's scans (and, for host texts, its copy) on its slot.
+int issue(ac_server *s, Request *r, bool copy_text, std::string &err) {
+    Slot &sl = s->slots[size_t(r->slot)];
+    const ac_automaton *a = s->autos[r->automaton];
+    acm::ScanConfig cfg;
+    cfg.algo = AC_ALGO_DFA;
+    cfg.placement = a->placement;
+    int rc = acm::launch_zero_count(sl.d_count, sl.scan, err);
+    if (rc != AC_OK) return rc;
+    const uint64_t P = s->piece;
+    r->pieces = uint32_t((r->n + P - 1) / P);
+    for (uint32_t p = 0; p < r->pieces; ++p) {
+        const uint64_t off = uint64_t(p) * P, len = std::min(P, r->n - off);
+        if (copy_text) {
+            hipError_t e = hipMemcpyAsync(const_cast<uint8_t *>(r->d_text) + off, r->src + off, len,
+                                          hipMemcpyHostToDevice, sl.copy);
+            if (e == hipSuccess) e = hipEventRecord(sl.piece[p % kPieceEvents], sl.copy);
+            if (e == hipSuccess) e = hipStreamWaitEvent(sl.scan, sl.piece[p % kPieceEvents], 0);
+            if (e != hipSuccess) {
+                err = std::string("text copy: ") + hipGetErrorString(e);
+                return AC_ERR_HIP;
+            }
+        }
+        acm::StreamArgs st;
+        st.base = off;
+        st.state_in = p ? sl.d_state + ((p - 1) & 1u) : nullptr;
+        st.state_out = p + 1 < r->pieces ? sl.d_state + (p & 1u) : nullptr;
+        rc = acm::launch_dfa_scan(a->dm, r->d_text + off, len, r->d_out, r->cap, sl.d_count, cfg, sl.scan, err,
+                                  st);
+        if (rc != AC_OK) return rc;
+    }
+    hipError_t e = hipMemcpyAsync(sl.h_count, sl.d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, sl.scan);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.scan);
+    if (e != hipSuccess) {
+        err = std::string("completion record: ") + hipGetErrorString(e);
+        return AC_ERR_HIP;
+    }
+    return AC_OK;
+}
+
+// Device memory for the request's text copy and match list; false if the
+// pool cannot hold them now.
+bool reserve(ac_server *s, Request *r) {
+    uint64_t t = kNone;
+    if (!r->on_device) {
+        t = s->pool.alloc(r->n);
+        if (t == kNone) return false;
+    }
+    const uint64_t cap = reservation(s, r);
+    const uint64_t o = s->pool.alloc(cap * sizeof(uint64_t));
+    if (o == kNone) {
+        if (t != kNone) s->pool.release(t);
+        return false;
+    }
+    if (!r->on_device) {
+        r->text_off = t;
+        r->d_text = s->pool_base + t;
+    }
+    r->out_off = o;
+    r->d_out = reinterpret_cast<uint64_t *>(s->pool_base + o);
+    r->cap = cap;
+    return true;
+}
+
+void start(ac_server *s, Request *r, int slot) {
+    r->slot = slot;
+    s->slots[size_t(slot)].req = r;
+    r->phase = Phase::Running;
+    r->t_admit = now_ns(s);
+    std::string err;
+    const int rc = issue(s, r, !r->on_device, err);
+    if (rc != AC_OK) {
+        // nothing after the failing call was queued; let the slot drain first
+        (void)hipStreamSynchronize(s->slots[size_t(slot)].scan);
+        (void)hipStreamSynchronize(s->slots[size_t(slot)].copy);
+        finish(s, r, rc, err);
+    } else {
+        s->running.push_back(r);
+        s->running_peak = std::max<uint64_t>(s->running_peak, s->running.size());
+    }
+}
+
+void admit(ac_server *s) {
+    std::vector<int> free_slots;
+    for (size_t i = 0; i < s->slots.size(); ++i)
+        if (!s->slots[i].req) free_slots.push_back(int(i));
+    const uint64_t now = now_ns(s);
+    auto it = s->queue.begin();
+    while (it != s->queue.end() && !free_slots.empty()) {
+        Request *r = *it;
+        if (r->t_submit > now) break;  // not arrived yet (the queue is in arrival order)
+        if (r->n == 0) {
+            r->t_admit = now_ns(s);
+            r->pieces = 0;
+            finish(s, r, AC_OK, "");
+            it = s->queue.erase(it);
+            continue;
+        }
+        if (reserve(s, r)) {
+            if (it != s->queue.begin()) ++s->queue.front()->bypassed;
+            start(s, r, free_slots.back());
+            free_slots.pop_back();
+            it = s->queue.erase(it);
+            continue;
+        }
+        // the head waits for memory; later requests may pass it a bounded
+        // number of times, then admission holds until the head fits
+        if (it == s->queue.begin() && r->bypassed >= kMaxBypass) break;
+        ++it;
+    }
+}
+
+// A slot's scans have finished: check the count against the reservation.
+void complete(ac_server *s, Request *r) {
+    Slot &sl = s->slots[size_t(r->slot)];
+    const uint64_t count = *sl.h_count;
+    if (count <= r->cap) {
+        r->n_matches = count;
+        // a finished list keeps only its own bytes of the budget
+        s->pool.shrink(r->out_off, count * sizeof(uint64_t));
+        r->cap = count;
+        const double seen = double(count) / double(std::max<uint64_t>(1, r->n));
+        double &est = s->rate[r->automaton];
+        est = std::max(seen, 0.9 * est + 0.1 * seen);
+        finish(s, r, AC_OK, "");
+        return;
+    }
+    // too many matches for the reservation: rescan into an exact list
+    s->pool.release(r->out_off);
+    r->out_off = kNone;
+    r->d_out = nullptr;
+    r->cap = count;
+    r->n_matches = count;
+    s->rate[r->automaton] = std::max(s->rate[r->automaton], double(count) / double(r->n));
+    r->phase = Phase::WaitMemory;
+    ++r->rescans;
+    ++s->rescans;
+}
+
+bool retry_rescan(ac_server *s, Request *r) {
+    const uint64_t o = s->pool.alloc(r->cap * sizeof(uint64_t));
+    if (o == kNone) return false;
+    r->out_off = o;
+    r->d_out = reinterpret_cast<uint64_t *>(s->pool_base + o);
+    r->phase = Phase::Running;
+    std::string err;
+    const int rc = issue(s, r, false, err);
+    if (rc != AC_OK) {
+        (void)hipStreamSynchronize(s->slots[size_t(r->slot)].scan);
+        finish(s, r, rc, err);
+        return false;
+    }
+    return true;
+}
+
+void worker_main(ac_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        bool progress = false;
+        for (size_t i = 0; i < s->running.size();) {
+            Request *r = s->running[i];
+            bool drop = false;
+            if (r->phase == Phase::Running) {
+                const hipError_t q = hipEventQuery(s->slots[size_t(r->slot)].done);
+                if (q == hipSuccess) {
+                    complete(s, r);
+                    progress = true;
+                    if (r->phase == Phase::WaitMemory) {
+                        retry_rescan(s, r);
+                    }
+                    drop = r->phase == Phase::Done;
+                } else if (q != hipErrorNotReady) {
+                    finish(s, r, AC_ERR_HIP, std::string("request scan: ") + hipGetErrorString(q));
+                    drop = true;
+                }
+            } else if (r->phase == Phase::WaitMemory) {
+                if (retry_rescan(s, r)) progress = true;
+                drop = r->phase == Phase::Done;
+            }
+            if (drop) {
+                s->running[i] = s->running.back();
+                s->running.pop_back();
+            } else {
+                ++i;
+            }
+        }
+        const size_t queued = s->queue.size();
+        admit(s);
+        progress |= s->queue.size() != queued;
+        if (s->stop && s->running.empty()) {
+            // shutting down with nothing on the device: whatever still waits
+            // for memory can no longer get it
+            for (Request *r : s->queue) finish(s, r, AC_ERR_BUSY, "server shut down before admission");
+            s->queue.clear();
+            break;
+        }
+        if (progress) continue;
+        // sleep until a completion may have happened (poll), the next
+        // scheduled arrival, or a submit / release / stop
+        const uint64_t now = now_ns(s);
+        uint64_t wake = s->running.empty() ? kNone : now + 20000;
+        if (!s->queue.empty() && s->queue.front()->t_submit > now)
+            wake = std::min(wake, s->queue.front()->t_submit);
+        if (wake == kNone)
+            s->cv_work.wait(lk);
+        else if (wake > now)
+            s->cv_work.wait_for(lk, std::chrono::nanoseconds(std::min<uint64_t>(wake - now, 20000)));
+    }
+}
+
+void destroy(ac_server *s) {
+    for (Slot &sl : s->slots) {
+        if (sl.scan) (void)hipStreamDestroy(sl.scan);
+        if (sl.copy) (void)hipStreamDestroy(sl.copy);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        for (hipEvent_t &e : sl.piece)
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (s->words) (void)hipFree(s->words);
+    if (s->h_counts) (void)hipHostFree(s->h_counts);
+    if (s->pool_base) (void)hipFree(s->pool_base);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac_serve_opts *opts,
+                    ac_server **out) {
+    if (!out) return set_error(AC_ERR_INVALID, "ac_serve_create: out is NULL");
+    *out = nullptr;
+    if (!autos || n_autos == 0) return set_error(AC_ERR_INVALID, "ac_serve_create: no automata");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(AC_ERR_HIP, "ac_serve_create: hipGetDevice failed");
+    for (uint32_t i = 0; i < n_autos; ++i)
+        if (!autos[i] || !autos[i]->on_device || autos[i]->device != dev)
+            return set_error(AC_ERR_INVALID, "ac_serve_create: automaton " + std::to_string(i) +
+                                                 " is NULL, host-only or on another device");
+    const uint64_t budget = opts && opts->hbm_budget ? opts->hbm_budget : (4ull << 30);
+    const uint32_t slots = opts && opts->max_inflight ? opts->max_inflight : 8u;
+    const uint64_t piece = opts && opts->piece_bytes ? opts->piece_bytes : (16u << 20);
+    const double rate = (opts && opts->match_ppm ? opts->match_ppm : 20000u) * 1e-6;
+    if (piece % 16 != 0) return set_error(AC_ERR_INVALID, "ac_serve_create: piece_bytes must be a multiple of 16");
+    if (slots > 64) return set_error(AC_ERR_INVALID, "ac_serve_create: at most 64 slots");
+
+    ac_server *s = new (std::nothrow) ac_server();
+    if (!s) return set_error(AC_ERR_NOMEM, "ac_serve_create: out of host memory");
+    s->device = dev;
+    s->autos.assign(autos, autos + n_autos);
+    s->rate.assign(n_autos, rate);
+    s->piece = piece;
+    s->t0 = Clock::now();
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s->pool_base), budget);
+    if (e != hipSuccess) {
+        s->pool_base = nullptr;
+        destroy(s);
+        return set_error(AC_ERR_NOMEM, std::string("ac_serve_create: device pool: ") + hipGetErrorString(e));
+    }
+    s->pool.init(budget);
+    // per slot: count (8 bytes) and two state words, 16 bytes in all
+    e = hipMalloc(&s->words, size_t(slots) * 16);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->h_counts), size_t(slots) * 8, 0);
+    s->slots.resize(slots);
+    for (uint32_t i = 0; i < slots && e == hipSuccess; ++i) {
+        Slot &sl = s->slots[i];
+        sl.d_count = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(s->words) + 16 * i);
+        sl.d_state = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(s->words) + 16 * i + 8);
+        sl.h_count = s->h_counts + i;
+        e = hipStreamCreateWithFlags(&sl.scan, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.copy, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        for (uint32_t k = 0; k < kPieceEvents && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&sl.piece[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        destroy(s);
+        return set_error(AC_ERR_HIP, std::string("ac_serve_create: ") + hipGetErrorString(e));
+    }
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        destroy(s);
+        return set_error(AC_ERR_NOMEM, "ac_serve_create: cannot start the scheduler thread");
+    }
+    *out = s;
+    return AC_OK;
+}
+
+int ac_serve_submit(ac_server *s, uint32_t automaton, const uint8_t *text, uint64_t n, int text_on_device,
+                    uint64_t arrival_ns, uint64_t *ticket) {
+    if (!s || !ticket) return set_error(AC_ERR_INVALID, "ac_serve_submit: NULL server or ticket");
+    if (automaton >= s->autos.size()) return set_error(AC_ERR_INVALID, "ac_serve_submit: no such automaton");
+    if (n > 0 && !text) return set_error(AC_ERR_INVALID, "ac_serve_submit: NULL text");
+    if (n >= (1ull << 32)) return set_error(AC_ERR_TOO_LARGE, "ac_serve_submit: text of 2^32 bytes or more");
+    if (text_on_device && n > 0 && (reinterpret_cast<uintptr_t>(text) & 15u))
+        return set_error(AC_ERR_INVALID, "ac_serve_submit: device text must be 16-byte aligned");
+    auto r = std::make_unique<Request>();
+    r->automaton = automaton;
+    r->src = text;
+    r->n = n;
+    r->on_device = text_on_device != 0;
+    if (r->on_device) r->d_text = text;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) return set_error(AC_ERR_INVALID, "ac_serve_submit: server is shutting down");
+    const uint64_t need = (r->on_device ? 0 : ((n + kAlign - 1) & ~(kAlign - 1))) +
+                          ((reservation(s, r.get()) * 8 + kAlign - 1) & ~(kAlign - 1));
+    if (need > s->pool.size())
+        return set_error(AC_ERR_TOO_LARGE, "ac_serve_submit: the request alone exceeds the HBM budget");
+    r->id = s->next_id++;
+    r->t_submit = std::max(arrival_ns, now_ns(s));
+    *ticket = r->id;
+    // the queue is kept in arrival order (FIFO among equal times)
+    auto pos = s->queue.end();
+    while (pos != s->queue.begin() && (*std::prev(pos))->t_submit > r->t_submit) --pos;
+    s->queue.insert(pos, r.get());
+    s->requests.emplace(r->id, std::move(r));
+    ++s->submitted;
+    s->cv_work.notify_one();
+    return AC_OK;
+}
+
+int ac_serve_wait(ac_server *s, uint64_t ticket, int64_t timeout_ms, ac_serve_result *res) {
+    if (!s || !res) return set_error(AC_ERR_INVALID, "ac_serve_wait: NULL server or result");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(AC_ERR_INVALID, "ac_serve_wait: unknown ticket");
+    Request *r = it->second.get();
+    auto done = [&] { return r->phase == Phase::Done; };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+        return set_error(AC_ERR_BUSY, "ac_serve_wait: request not finished within the timeout");
+    res->status = r->status;
+    res->automaton = r->automaton;
+    res->n = r->n;
+    res->d_matches = r->d_out;
+    res->n_matches = r->n_matches;
+    res->t_submit_ns = r->t_submit;
+    res->t_admit_ns = r->t_admit;
+    res->t_done_ns = r->t_done;
+    res->pieces = r->pieces;
+    res->rescans = r->rescans;
+    if (r->status != AC_OK) return set_error(r->status, "ac_serve_wait: request failed: " + r->message);
+    return AC_OK;
+}
+
+int ac_serve_release(ac_server *s, uint64_t ticket) {
+    if (!s) return set_error(AC_ERR_INVALID, "ac_serve_release: NULL server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(AC_ERR_INVALID, "ac_serve_release: unknown ticket");
+    Request *r = it->second.get();
+    if (r->phase != Phase::Done) return set_error(AC_ERR_BUSY, "ac_serve_release: request still running");
+    if (r->out_off != kNone) s->pool.release(r->out_off);
+    s->requests.erase(it);
+    s->cv_work.notify_one();  // memory came free
+    return AC_OK;
+}
+
+int ac_serve_stats(ac_server *s, ac_serve_stats_t *st) {
+    if (!s || !st) return set_error(AC_ERR_INVALID, "ac_serve_stats: NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    st->submitted = s->submitted;
+    st->completed = s->completed;
+    st->failed = s->failed;
+    st->queued = s->queue.size();
+    st->running = s->running.size();
+    st->rescans = s->rescans;
+    st->pool_bytes = s->pool.size();
+    st->pool_used = s->pool.used();
+    st->pool_peak = s->pool.peak();
+    st->running_peak = s->running_peak;
+    return AC_OK;
+}
+
+uint64_t ac_serve_now_ns(const ac_server *s) { return s ? now_ns(s) : 0; }
+
+void ac_serve_destroy(ac_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv_work.notify_one();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    destroy(s);
+}
+
+}  // extern "C"

@@ -184,3 +184,51 @@ def batched_workload(n_texts: int = 4096, n_sets: int = 16, len_lo_log2: int = 1
         ends = np.cumsum(lengths)
         sets.append([pool[e - l:e].tobytes() for e, l in zip(ends, lengths)])
     return texts, sets, text_set
+
+
+@dataclass
+class ServedWorkload:
+    """Requests for the served form. Request i scans bytes
+    [offset[i], offset[i] + length[i]) of the text of its alphabet
+    (``texts[alpha[i]]``, 0 = DNA, 1 = protein) with automaton ``automaton[i]``;
+    sets[j] is automaton j's pattern set and set_alpha[j] its alphabet."""
+    texts: list[np.ndarray]
+    sets: list[list[bytes]]
+    set_alpha: np.ndarray
+    alpha: np.ndarray
+    automaton: np.ndarray
+    offset: np.ndarray
+    length: np.ndarray
+
+
+def served_workload(n_requests: int = 512, text_bytes: int = 1 << 26, len_lo_log2: int = 10,
+                    len_hi_log2: int = 26, n_sets: int = 8, set_lo: int = 1000, set_hi: int = 50_000,
+                    seed: int = 5) -> ServedWorkload:
+    """Request lengths log-uniform in [2**len_lo_log2, 2**len_hi_log2], half DNA
+    and half protein-shaped; ``n_sets`` pattern sets with sizes log-spaced in
+    [set_lo, set_hi], alternately DNA (lengths 8-32, uniform letters) and
+    protein (lengths 6-20, the skewed letter law); each request names a set of
+    its own alphabet uniformly at random. Request texts are windows, at
+    16-byte aligned random offsets, of one text per alphabet of ``text_bytes``
+    bytes (at least the longest request)."""
+    rng = np.random.default_rng(3000 + seed)
+    texts = [dna_text(text_bytes, 3100 + seed), protein_text(text_bytes, 3200 + seed)]
+    sizes = np.round(np.geomspace(set_lo, set_hi, n_sets)).astype(np.int64)
+    set_alpha = np.arange(n_sets) % 2
+    sets = []
+    for j, sz in enumerate(sizes):
+        alphabet, lo, hi = (DNA, 8, 32) if set_alpha[j] == 0 else (PROTEIN, 6, 20)
+        lengths = rng.integers(lo, hi + 1, size=int(sz))
+        pool = _letters(rng, alphabet, int(lengths.sum()))
+        ends = np.cumsum(lengths)
+        sets.append([pool[e - L:e].tobytes() for e, L in zip(ends, lengths)])
+    u = rng.random(n_requests)
+    length = np.floor(2.0 ** (len_lo_log2 + (len_hi_log2 - len_lo_log2) * u)).astype(np.int64)
+    length = np.minimum(length, text_bytes)
+    alpha = rng.integers(0, 2, size=n_requests)
+    automaton = np.empty(n_requests, dtype=np.int64)
+    for i in range(n_requests):
+        own = np.nonzero(set_alpha == alpha[i])[0]
+        automaton[i] = own[rng.integers(0, len(own))]
+    offset = (rng.integers(0, text_bytes - length + 1) // 16) * 16
+    return ServedWorkload(texts, sets, set_alpha, alpha, automaton, offset.astype(np.int64), length)
