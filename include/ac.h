@@ -147,7 +147,7 @@ typedef struct {
     uint32_t block;     /* threads per workgroup; 0 = the placement's own (the only
                            value accepted otherwise) */
     uint32_t placement; /* 0 = the automaton's; else an AC_PLACE_* override */
-    uint32_t walkers;   /* DFA: chunks walked in lockstep by each lane (1, 2 or 4);
+    uint32_t walkers;   /* DFA: chunks walked in lockstep by each lane (1 to 4);
                            0 = auto */
     uint32_t block_bytes; /* DFA: text bytes a walker loads at once (64 or 128);
                              0 = auto */
@@ -236,7 +236,7 @@ typedef struct ac_batch ac_batch;
 typedef struct {
     uint32_t placement; /* AC_PLACE_AUTO (LDS_HOT when every automaton has an LDS
                            image, else GLOBAL), AC_PLACE_LDS_HOT or AC_PLACE_GLOBAL */
-    uint32_t walkers;   /* chunks walked per lane (1, 2, 4); 0 = by placement */
+    uint32_t walkers;   /* chunks walked per lane (1 to 4); 0 = by placement */
     uint32_t chunk;     /* end positions per work item; 0 = from the batch size */
     uint32_t reserved;
 } ac_batch_tune;

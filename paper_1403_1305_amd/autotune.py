@@ -1,7 +1,7 @@
 """Autotuner for the batched scan.
 
 Picks the table placement (LDS image + global cold rows, or global table),
-the number of chunks each lane walks (1, 2 or 4) and the chunk length for a
+the number of chunks each lane walks (1 to 4) and the chunk length for a
 batch by timing candidate plans on the device with HIP events, then caches
 the winner under a key of (GPU architecture, byte-class scheme, largest
 automaton's state count, total text bytes, number of texts), each size
@@ -27,7 +27,7 @@ from . import ac
 CACHE_ENV = "AC_TUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1403_1305_amd", "batch_tune.json")
 CHUNKS = (0, 128, 256, 512, 1024, 2048, 4096)  # 0 = the plan's own choice
-WALKERS = (1, 2, 4)
+WALKERS = (1, 2, 3, 4)
 
 
 def _log2_bucket(x: int) -> int:

@@ -140,8 +140,8 @@ int ac_batch_create(const ac_automaton *const *autos, uint32_t n_autos, const ui
         return set_error(AC_ERR_INVALID, "ac_batch_create: LDS_HOT needs every automaton built with an "
                                          "LDS image (ac_build with AC_PLACE_LDS_HOT)");
     const uint32_t K = tune && tune->walkers ? tune->walkers : (place == AC_PLACE_LDS_HOT ? 2u : 1u);
-    if (K != 1 && K != 2 && K != 4) return set_error(AC_ERR_INVALID, "ac_batch_create: walkers must be 1, 2 or 4");
-    const uint32_t bb = K == 4 ? 64u : 128u;
+    if (K < 1 || K > 4) return set_error(AC_ERR_INVALID, "ac_batch_create: walkers must be 1, 2, 3 or 4");
+    const uint32_t bb = K >= 3 ? 64u : 128u;
     const bool hashed = autos[0]->m.hashed;
     const int l2 = hashed ? int(autos[0]->m.log2_cols) : -1;
 

@@ -45,8 +45,8 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
     // default walkers per lane: two hide more lookup latency than one except
     // when every lookup goes to global memory
     const uint32_t K = cfg.walkers ? cfg.walkers : (cfg.placement == AC_PLACE_GLOBAL ? 1u : 2u);
-    if (K != 1 && K != 2 && K != 4) {
-        err = "ac_scan: walkers per lane must be 1, 2 or 4";
+    if (K < 1 || K > 4) {
+        err = "ac_scan: walkers per lane must be 1, 2, 3 or 4";
         return AC_ERR_INVALID;
     }
     const uint32_t block = block_for(cfg.placement, K);
@@ -63,7 +63,7 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
     }
     // text block: whole cache lines (128 B, one buffer: a line is fetched
     // once) unless four walkers need the registers (64 B, one buffer)
-    const uint32_t bb = cfg.block_bytes ? cfg.block_bytes : (K == 4 ? 64u : 128u);
+    const uint32_t bb = cfg.block_bytes ? cfg.block_bytes : (K >= 3 ? 64u : 128u);
     if (bb != 64 && bb != 128) {
         err = "ac_scan: block_bytes must be 64 or 128";
         return AC_ERR_INVALID;

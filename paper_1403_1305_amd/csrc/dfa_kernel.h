@@ -545,8 +545,9 @@ inline void fill_machine_args(const DeviceMachine &dm, DfaArgs &a) {
 using DfaKernel = void (*)(DfaArgs);
 
 // Kernel for one walker count, block size and class scheme of a placement.
-// KIND: 0 = 64-byte blocks, two buffers; 1 = 128-byte blocks, one buffer;
-// 2 = 64-byte blocks, one buffer (four walkers).
+// One or two walkers: 128-byte blocks in one buffer, or 64-byte blocks in two;
+// three or four walkers: 64-byte blocks in one buffer (the registers for
+// longer blocks would spill).
 template <int PLACE>
 DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) {
     const bool hashed = dm.hashed;
@@ -556,11 +557,12 @@ DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) 
     return dfa_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
 #define AC_DFA_CASE(KK, LL, HH)                                                                     \
     if (K == KK && l2 == LL && hashed == HH) {                                                      \
-        if constexpr (KK == 4) { AC_DFA_V(KK, LL, HH, 1, 4) }                                       \
+        if constexpr (KK >= 3) { AC_DFA_V(KK, LL, HH, 1, 4) }                                       \
         else if (block_bytes == 128) { AC_DFA_V(KK, LL, HH, 1, 8) }                                 \
         else { AC_DFA_V(KK, LL, HH, 2, 4) }                                                         \
     }
-#define AC_DFA_KS(LL, HH) AC_DFA_CASE(1, LL, HH) AC_DFA_CASE(2, LL, HH) AC_DFA_CASE(4, LL, HH)
+#define AC_DFA_KS(LL, HH) \
+    AC_DFA_CASE(1, LL, HH) AC_DFA_CASE(2, LL, HH) AC_DFA_CASE(3, LL, HH) AC_DFA_CASE(4, LL, HH)
     AC_DFA_KS(-1, false)
     AC_DFA_KS(0, true)
     AC_DFA_KS(1, true)
@@ -583,10 +585,10 @@ BatchKernel select_batch_for(bool hashed, int l2, uint32_t K, uint32_t block_byt
     return batch_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
 #define AC_B_CASE(KK, LL, HH)                                                                       \
     if (K == KK && l2 == LL && hashed == HH) {                                                      \
-        if constexpr (KK == 4) { AC_B_V(KK, LL, HH, 1, 4) }                                         \
+        if constexpr (KK >= 3) { AC_B_V(KK, LL, HH, 1, 4) }                                         \
         else { AC_B_V(KK, LL, HH, 1, 8) }                                                           \
     }
-#define AC_B_KS(LL, HH) AC_B_CASE(1, LL, HH) AC_B_CASE(2, LL, HH) AC_B_CASE(4, LL, HH)
+#define AC_B_KS(LL, HH) AC_B_CASE(1, LL, HH) AC_B_CASE(2, LL, HH) AC_B_CASE(3, LL, HH) AC_B_CASE(4, LL, HH)
     AC_B_KS(-1, false)
     AC_B_KS(0, true)
     AC_B_KS(1, true)

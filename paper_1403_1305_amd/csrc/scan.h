@@ -27,7 +27,7 @@ struct ScanConfig {
     uint32_t algo = 0;       // AC_ALGO_*
     uint32_t chunk = 0;      // DFA chunk bytes (multiple of 16), 0 = auto
     uint32_t block = 0;      // threads per workgroup, 0 = auto
-    uint32_t walkers = 0;    // DFA chunks walked per lane (1, 2, 4), 0 = auto
+    uint32_t walkers = 0;    // DFA chunks walked per lane (1 to 4), 0 = auto
     uint32_t block_bytes = 0;  // DFA text bytes per walker load (64, 128), 0 = auto
     uint32_t placement = 0;  // resolved AC_PLACE_* (never AUTO here)
 };

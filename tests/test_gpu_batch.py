@@ -96,7 +96,7 @@ def dna_batch():
 
 
 @pytest.mark.parametrize("placement", [ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_HOT])
-@pytest.mark.parametrize("walkers", [0, 1, 2, 4])
+@pytest.mark.parametrize("walkers", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("chunk", [0, 128, 1024])
 def test_batch_matches_oracle(dna_batch, placement, walkers, chunk):
     texts, sets, text_set, autos, expect = dna_batch
@@ -150,7 +150,7 @@ def test_batch_mixed_sizes_and_reloads():
     autos = [build(s) for s in sets]
     buf, offs, _ = ac.pack_texts(texts)
     expect = expected(texts, sets, text_set, offs)
-    for w in (1, 2, 4):
+    for w in (1, 2, 3, 4):
         r = BatchRun(autos, texts, text_set, tune=tune(ac.AC_PLACE_LDS_HOT, w, 16))
         assert r.info["n_tasks"] >= len(sets)
         assert np.array_equal(r.scan(), expect), w

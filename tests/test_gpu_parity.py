@@ -104,7 +104,7 @@ def test_small_dna(small, algo, placement):
     assert got.size == expect.size and np.array_equal(got, expect)
 
 
-@pytest.mark.parametrize("walkers", [1, 2, 4])
+@pytest.mark.parametrize("walkers", [1, 2, 3, 4])
 @pytest.mark.parametrize("chunk", [16, 32, 48, 64, 80, 1024, 4096, 1 << 20])
 def test_small_dna_chunk_lengths(small, chunk, walkers):
     w, expect = small
@@ -147,7 +147,7 @@ def test_chunk_boundaries(chunk, m):
     expect = oracle.oracle_match(text, pats)
     for placement in (ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_HOT):
         a = build(pats, placement=placement, hot_states=7 if placement == ac.AC_PLACE_LDS_HOT else 0)
-        for walkers in (1, 2, 4):
+        for walkers in (1, 2, 3, 4):
             for bb in (64, 128):
                 assert np.array_equal(gpu_keys(a, text, chunk=chunk, walkers=walkers, block_bytes=bb),
                                       expect), (chunk, m, placement, walkers, bb)
@@ -164,7 +164,7 @@ def test_ragged_and_tiny_texts(n):
         a = build(pats, placement=placement)
         for algo in (ac.AC_ALGO_DFA, ac.AC_ALGO_PFAC):
             for chunk in (0, 16, 32):
-                for walkers in ((1, 2, 4) if algo == ac.AC_ALGO_DFA else (0,)):
+                for walkers in ((1, 2, 3, 4) if algo == ac.AC_ALGO_DFA else (0,)):
                     if algo == ac.AC_ALGO_PFAC and chunk:
                         continue
                     for bb in ((64, 128) if algo == ac.AC_ALGO_DFA else (0,)):
