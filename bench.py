@@ -285,14 +285,65 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     }
 
 
+BUILD_DESC = ("total-time throughput, eq. (1): input bytes / (machine build + scan), DNA pattern sets of "
+              "0.5M / 1M / 1.5M random patterns of 16-24 bytes (10 / 20 / 30 MB) and i.i.d. DNA inputs "
+              "of 70 KB and 100 KB")
+
+
+def bench_build(args, torch, ac, stream, sizes=(500_000, 1_000_000, 1_500_000), inputs=(70_000, 100_000)):
+    """Build time and total-time throughput (eq. 1): the full machine (goto,
+    failure, output, DFA) with the DFA scan against the failure-less machine
+    (goto and own outputs only) with the PFAC scan, for growing pattern sets.
+    Builds run on the host and include the upload of the tables."""
+    import numpy as np
+
+    from synth import DNA, dna_text, random_pattern_csr
+
+    texts = {n: torch.from_numpy(dna_text(n, 77)).to("cuda") for n in inputs}
+    out = torch.empty(1 << 22, dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rows = []
+    for n_pat in sizes:
+        pat, off = random_pattern_csr(n_pat, 16, 24, DNA, 4000 + n_pat // 1000)
+        rec = {"patterns": n_pat, "pattern_mb": round(int(off[-1]) / 1e6, 1)}
+        for kind, flags, algo in (("dfa", 0, ac.AC_ALGO_DFA), ("pfac_goto_only", ac.AC_BUILD_GOTO_ONLY,
+                                                                   ac.AC_ALGO_PFAC)):
+            log(f"build {n_pat} {kind}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a = ac.ac_build(pat, off, opts=ac._opts(flags=flags), stream=stream)
+            build_s = time.perf_counter() - t0
+            info = ac.ac_info(a)
+            sub = {"build_s": round(build_s, 3), "host_build_s": round(info["build_ms"] / 1e3, 3),
+                   "states": info["n_states"]}
+            opts = ac._scan_opts(algo)
+            for n in inputs:
+                ac.ac_scan(a, texts[n], n, out, out.numel(), count, opts, stream)  # warm-up
+                _, ms = time_steps(lambda i: ac.ac_scan(a, texts[n], n, out, out.numel(), count, opts, stream),
+                                   5, stream, torch)
+                scan_s = float(np.median(ms)) / 1e3
+                sub[f"scan_ms_{n // 1000}k"] = round(scan_s * 1e3, 4)
+                sub[f"throughput_Bps_{n // 1000}k"] = round(n / (build_s + scan_s), 1)
+                sub[f"matches_{n // 1000}k"] = int(count.item())
+            rec[kind] = sub
+            del a
+        for n in inputs:
+            k = f"throughput_Bps_{n // 1000}k"
+            rec[f"ratio_{n // 1000}k"] = round(rec["pfac_goto_only"][k] / rec["dfa"][k], 3)
+        rows.append(rec)
+        log(rec)
+    return {"workload": f"build: {BUILD_DESC}", "unit": "B/s", "rows": rows}
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched", "served"])
+    p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched", "served", "build"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched sub-benchmark")
     p.add_argument("--no-served", action="store_true", help="skip the served sub-benchmark")
+    p.add_argument("--no-build", action="store_true", help="skip the build-time sub-benchmark")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)
@@ -328,6 +379,19 @@ def main():
                           "automata": b["automata"], "kernel": "batch_scan"},
                "pct_hbm_peak": round(100 * b["value"] / HBM_PEAK_GBS, 2), "roofline": b["roofline"],
                "cpu_baseline": None, "batched": b}
+        print(json.dumps(rec), flush=True)
+        return
+
+    if args.workload == "build":
+        v = bench_build(args, torch, ac, stream)
+        last = v["rows"][-1]
+        rec = {"metric": "total-time throughput, eq. (1), build + scan (failure-less PFAC vs full DFA)",
+               "value": last["pfac_goto_only"]["throughput_Bps_100k"], "unit": "B/s", "n_gpus": 1,
+               "steps": 5, "warmup": 1, "ms_per_step": round(last["pfac_goto_only"]["build_s"] * 1e3, 2),
+               "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "u8",
+               "data": "synthetic", "config": {"workload": v["workload"], "patterns": last["patterns"],
+                                               "n_bytes": 100_000, "kernel": "pfac_scan"},
+               "roofline": None, "cpu_baseline": None, "build": v}
         print(json.dumps(rec), flush=True)
         return
 
@@ -407,6 +471,10 @@ def main():
     if not args.no_batched:
         torch.cuda.empty_cache()
         batched = bench_batched(args, torch, ac, stream)
+    build = None
+    if not args.no_build:
+        torch.cuda.empty_cache()
+        build = bench_build(args, torch, ac, stream)
     served = None
     if not args.no_served:
         torch.cuda.empty_cache()
@@ -442,6 +510,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,
+        "build": build,
     }
     print(json.dumps(rec), flush=True)
 

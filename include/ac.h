@@ -63,8 +63,16 @@ typedef struct {
     uint32_t hot_states;  /* cap on states in the LDS_HOT image; 0 = as many as fit */
     uint32_t lds_bytes;   /* LDS budget for the table image; 0 = 151 KiB (the rest of
                              the 160 KiB holds per-wave match queues) */
-    uint32_t reserved;
+    uint32_t flags;       /* AC_BUILD_* bits */
 } ac_build_opts;
+
+enum {
+    /* Failure-less machine only (Sec. II.B): the goto function and the
+     * patterns ending at each state, without failure function, output unions
+     * or full DFA. Cheaper to build (Sec. IV.A, the cost the paper reduces);
+     * such an automaton scans with AC_ALGO_PFAC only. */
+    AC_BUILD_GOTO_ONLY = 1
+};
 
 typedef struct {
     uint64_t n_states;     /* states of the machine (trie nodes, root = 0) */
@@ -76,9 +84,11 @@ typedef struct {
     uint32_t hot_states;   /* rows in the LDS_HOT image (0 if none) */
     uint32_t class_shift;  /* byte -> column is (b >> shift) & (n_cols-1) when */
     uint32_t class_hashed; /*   class_hashed is 1; else a 256-entry map */
-    uint64_t table_bytes;  /* device bytes of the DFA table */
+    uint64_t table_bytes;  /* device bytes of the DFA table (0 for goto-only) */
     uint64_t out_entries;  /* total entries of all output sets */
     double build_ms;       /* host time spent constructing the machine */
+    uint32_t goto_only;    /* 1 if built with AC_BUILD_GOTO_ONLY */
+    uint32_t reserved;
 } ac_info_t;
 
 /*

@@ -33,6 +33,8 @@ AC_PLACE_LDS_HOT = 3
 AC_ALGO_DFA = 0
 AC_ALGO_PFAC = 1
 
+AC_BUILD_GOTO_ONLY = 1
+
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
     AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP = range(9)
 
@@ -48,7 +50,7 @@ class AcError(RuntimeError):
 
 class ac_build_opts(ctypes.Structure):
     _fields_ = [("placement", ctypes.c_uint32), ("hot_states", ctypes.c_uint32),
-                ("lds_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("lds_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class ac_info_t(ctypes.Structure):
@@ -57,7 +59,8 @@ class ac_info_t(ctypes.Structure):
                 ("m_max", ctypes.c_uint32), ("placement", ctypes.c_uint32),
                 ("hot_states", ctypes.c_uint32), ("class_shift", ctypes.c_uint32),
                 ("class_hashed", ctypes.c_uint32), ("table_bytes", ctypes.c_uint64),
-                ("out_entries", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
+                ("out_entries", ctypes.c_uint64), ("build_ms", ctypes.c_double),
+                ("goto_only", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ac_scan_opts(ctypes.Structure):
@@ -202,8 +205,8 @@ class Automaton:
         return ctypes.c_void_p(self.handle)
 
 
-def _opts(placement=AC_PLACE_AUTO, hot_states=0, lds_bytes=0):
-    return ac_build_opts(placement, hot_states, lds_bytes, 0)
+def _opts(placement=AC_PLACE_AUTO, hot_states=0, lds_bytes=0, flags=0):
+    return ac_build_opts(placement, hot_states, lds_bytes, flags)
 
 
 def ac_build(pat_bytes, pat_off, n_patterns: int | None = None, opts: ac_build_opts | None = None,

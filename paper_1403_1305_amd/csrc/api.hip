@@ -57,6 +57,8 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
     *out = nullptr;
     const uint32_t place = opts ? opts->placement : AC_PLACE_AUTO;
     if (place > AC_PLACE_LDS_HOT) return fail(AC_ERR_INVALID, "ac_build: unknown placement");
+    const uint32_t flags = opts ? opts->flags : 0u;
+    if (flags & ~uint32_t(AC_BUILD_GOTO_ONLY)) return fail(AC_ERR_INVALID, "ac_build: unknown flags");
     a = new (std::nothrow) ac_automaton();
     if (!a) return fail(AC_ERR_NOMEM, "ac_build: out of host memory");
     const uint32_t budget = lds_budget(opts);
@@ -66,6 +68,7 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
         plan.max_states = opts ? opts->hot_states : 0;
         plan.only_if_needed = place == AC_PLACE_AUTO;
     }
+    plan.goto_only = (flags & AC_BUILD_GOTO_ONLY) != 0;
     std::string err;
     int rc;
     try {
@@ -187,7 +190,9 @@ int ac_info(const ac_automaton *a, ac_info_t *info) {
     info->hot_states = a->m.hot_states;
     info->class_shift = a->m.hash_shift;
     info->class_hashed = a->m.hashed ? 1u : 0u;
-    info->table_bytes = uint64_t(a->m.n_states) * a->m.n_cols * 4ull;
+    info->table_bytes = a->m.goto_only ? 0ull : uint64_t(a->m.n_states) * a->m.n_cols * 4ull;
+    info->goto_only = a->m.goto_only ? 1u : 0u;
+    info->reserved = 0;
     info->out_entries = a->m.out_ids.size();
     info->build_ms = a->m.build_ms;
     return AC_OK;
@@ -238,6 +243,8 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         want = opts->placement;
     }
     if (cfg.algo > AC_ALGO_PFAC) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
+    if (cfg.algo == AC_ALGO_DFA && a->m.goto_only)
+        return fail(AC_ERR_INVALID, "ac_scan: a goto-only automaton scans with AC_ALGO_PFAC only");
     if (!resolve_placement(a, want, cfg.placement))
         return fail(AC_ERR_INVALID, "ac_scan: placement not available for this automaton");
     int dev = -1;
@@ -259,6 +266,7 @@ int ac_scan_stream(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uin
                    void *stream) {
     if (!a || !d_count) return fail(AC_ERR_INVALID, "ac_scan_stream: NULL automaton or count");
     if (!a->on_device) return fail(AC_ERR_INVALID, "ac_scan_stream: automaton has no device tables");
+    if (a->m.goto_only) return fail(AC_ERR_INVALID, "ac_scan_stream: a goto-only automaton has no DFA");
     if (n > 0 && !d_text) return fail(AC_ERR_INVALID, "ac_scan_stream: NULL text");
     if (capacity > 0 && !d_matches) return fail(AC_ERR_INVALID, "ac_scan_stream: NULL match buffer");
     if (base + n >= (1ull << 32) || base >= (1ull << 32))

@@ -122,9 +122,9 @@ int ac_batch_create(const ac_automaton *const *autos, uint32_t n_autos, const ui
     bool all_images = true;
     for (uint32_t i = 0; i < n_autos; ++i) {
         const ac_automaton *a = autos[i];
-        if (!a || !a->on_device || a->device != dev)
+        if (!a || !a->on_device || a->device != dev || a->m.goto_only)
             return set_error(AC_ERR_INVALID, "ac_batch_create: automaton " + std::to_string(i) +
-                                                 " is NULL, host-only or on another device");
+                                                 " is NULL, host-only, goto-only or on another device");
         if (a->m.hashed != autos[0]->m.hashed ||
             (a->m.hashed && a->m.log2_cols != autos[0]->m.log2_cols))
             return set_error(AC_ERR_INVALID,

@@ -153,14 +153,16 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     // ---- failure function and full DFA, row by row in breadth-first order.
     // A row only reads the row of its failure state, which is shallower and
     // therefore already final.
-    std::vector<uint32_t> delta(size_t(S) * C);
-    std::vector<uint32_t> fail(S, 0);
-    for (uint32_t c = 0; c < C; ++c) {
+    const bool full = !plan.goto_only;
+    m.goto_only = plan.goto_only;
+    std::vector<uint32_t> delta(full ? size_t(S) * C : 0);
+    std::vector<uint32_t> fail(full ? S : 0, 0);
+    for (uint32_t c = 0; c < C && full; ++c) {
         int32_t w = child[c];
         delta[c] = w >= 0 ? uint32_t(w) : 0u;
         if (w >= 0) fail[w] = 0;
     }
-    for (uint32_t b = 1; b < S; ++b) {
+    for (uint32_t b = 1; b < S && full; ++b) {
         const uint32_t *frow = &delta[size_t(fail[b]) * C];
         uint32_t *row = &delta[size_t(b) * C];
         for (uint32_t c = 0; c < C; ++c) {
@@ -186,6 +188,10 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     }
     std::vector<uint32_t> out_off(S + 1, 0);
     std::vector<uint32_t> out_ids;
+    if (!full) {  // failure-less: a state outputs the patterns ending there
+        out_off = own_off;
+        out_ids = own_ids;
+    } else {
     out_ids.reserve(n);
     for (uint32_t b = 0; b < S; ++b) {
         out_off[b] = uint32_t(out_ids.size());
@@ -203,6 +209,7 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     }
     // out_off[b+1] of the last written state is also the final sentinel
     out_off[S] = uint32_t(out_ids.size());
+    }
     auto accepts = [&](uint32_t b) { return out_off[b + 1] > out_off[b]; };
 
     // ---- final numbering, in ranges:
@@ -246,7 +253,16 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         if (image)
             for (uint32_t i = 0; i < H; ++i)
                 for (uint32_t c = 0; c < C; ++c) {
-                    const uint32_t t = delta[size_t(cand[i]) * C + c];
+                    // a hot row's successors: DFA targets, or goto children
+                    // (a goto child is also the DFA target of its column)
+                    uint32_t t;
+                    if (full) {
+                        t = delta[size_t(cand[i]) * C + c];
+                    } else {
+                        const int32_t w = child[size_t(cand[i]) * C + c];
+                        if (w < 0) continue;
+                        t = uint32_t(w);
+                    }
                     if (!mark[t] && !accepts(t)) {
                         mark[t] = 2;
                         ++extra;
@@ -287,7 +303,7 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
 
     // ---- device tables in final ids
     m.n_states = S;
-    m.dfa.assign(size_t(S) * C, 0);
+    m.dfa.assign(full ? size_t(S) * C : 0, 0);
     m.go.assign(size_t(S) * C, 0);
     m.out_off.assign(S + 1, 0);
     m.own_off.assign(S + 1, 0);
@@ -298,8 +314,10 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     for (uint32_t f = 0; f < S; ++f) {
         uint32_t b = inv[f];
         for (uint32_t c = 0; c < C; ++c) {
-            uint32_t t = delta[size_t(b) * C + c];
-            m.dfa[size_t(f) * C + c] = perm[t] | (accepts(t) ? kAccept : 0u);
+            if (full) {
+                const uint32_t t = delta[size_t(b) * C + c];
+                m.dfa[size_t(f) * C + c] = perm[t] | (accepts(t) ? kAccept : 0u);
+            }
             int32_t w = child[size_t(b) * C + c];
             if (w >= 0)
                 m.go[size_t(f) * C + c] = perm[w] | (own_off[w + 1] > own_off[w] ? kAccept : 0u);
@@ -310,12 +328,12 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         m.own_off[f + 1] = uint32_t(m.own_ids.size());
     }
     m.hot_states = H;
-    m.hot_dfa.assign(size_t(H) * C, 0);
+    m.hot_dfa.assign(full ? size_t(H) * C : 0, 0);
     m.hot_go.assign(size_t(H) * C, 0);
     for (uint32_t f = 0; f < H; ++f)
         for (uint32_t c = 0; c < C; ++c) {
             // successors of hot rows were numbered below kHotIdLimit above
-            m.hot_dfa[size_t(f) * C + c] = uint16_t(m.dfa[size_t(f) * C + c] & kStateMask);
+            if (full) m.hot_dfa[size_t(f) * C + c] = uint16_t(m.dfa[size_t(f) * C + c] & kStateMask);
             m.hot_go[size_t(f) * C + c] = uint16_t(m.go[size_t(f) * C + c] & kStateMask);
         }
     // 16-bit images are copied as 32-bit words: pad them to whole words

@@ -39,6 +39,7 @@ struct Machine {
     uint8_t hash_letter[8] = {0};  // the pattern byte owning each hashed column (hashed only)
     uint8_t cmap[256];        // byte -> column, kNoClass if absent from all patterns
 
+    bool goto_only = false;   // built without failure function and DFA (dfa is empty)
     // Full DFA: dfa[s * n_cols + c] = delta(s, c) | kAccept if it is final.
     std::vector<uint32_t> dfa;
     // Output sets in CSR form, ids ascending: out(s) = out_ids[out_off[s] .. out_off[s+1]).
@@ -68,6 +69,10 @@ struct HotPlan {
     uint32_t lds_bytes = 0;      // bytes the image may take, 256 of them for the byte map; 0 = none
     uint32_t max_states = 0;     // cap on its rows, 0 = none
     bool only_if_needed = true;  // skip it when the whole 32-bit table fits lds_bytes
+    // Build the goto function and the patterns ending at each state only: no
+    // failure function, no output unions, no full DFA (the failure-less machine
+    // of Sec. II.B, all that the per-start-position matcher needs).
+    bool goto_only = false;
 };
 
 // Returns 0 or a negative AC_ERR_* code with `err` set. Without an image,

@@ -438,9 +438,9 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return set_error(AC_ERR_HIP, "ac_serve_create: hipGetDevice failed");
     for (uint32_t i = 0; i < n_autos; ++i)
-        if (!autos[i] || !autos[i]->on_device || autos[i]->device != dev)
+        if (!autos[i] || !autos[i]->on_device || autos[i]->device != dev || autos[i]->m.goto_only)
             return set_error(AC_ERR_INVALID, "ac_serve_create: automaton " + std::to_string(i) +
-                                                 " is NULL, host-only or on another device");
+                                                 " is NULL, host-only, goto-only or on another device");
     const uint64_t budget = opts && opts->hbm_budget ? opts->hbm_budget : (4ull << 30);
     const uint32_t slots = opts && opts->max_inflight ? opts->max_inflight : 8u;
     const uint64_t piece = opts && opts->piece_bytes ? opts->piece_bytes : (16u << 20);

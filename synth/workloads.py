@@ -232,3 +232,14 @@ def served_workload(n_requests: int = 512, text_bytes: int = 1 << 26, len_lo_log
         automaton[i] = own[rng.integers(0, len(own))]
     offset = (rng.integers(0, text_bytes - length + 1) // 16) * 16
     return ServedWorkload(texts, sets, set_alpha, alpha, automaton, offset.astype(np.int64), length)
+
+
+def random_pattern_csr(n: int, lo: int, hi: int, alphabet: bytes, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """n random patterns with lengths uniform in [lo, hi], i.i.d. letters of
+    ``alphabet`` (its letter law), as concatenated bytes and n + 1 offsets:
+    the large pattern sets of the build-time measurements."""
+    rng = np.random.default_rng(seed)
+    lengths = rng.integers(lo, hi + 1, size=n)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lengths, out=off[1:])
+    return _letters(rng, alphabet, int(off[-1])), off

@@ -360,3 +360,25 @@ def test_stream_rejects_pfac_and_aliasing():
         ac.ac_scan_stream(a, d, 32, 0, None, st, out, 64, count, opts=ac._scan_opts(ac.AC_ALGO_PFAC))
     with pytest.raises(ac.AcError):
         ac.ac_scan_stream(a, d, 32, 0, st, st, out, 64, count)
+
+
+# ---------------------------------------------------------------- failure-less build
+
+@pytest.mark.parametrize("placement", [ac.AC_PLACE_AUTO, ac.AC_PLACE_GLOBAL, ac.AC_PLACE_LDS_FULL,
+                                       ac.AC_PLACE_LDS_HOT])
+def test_goto_only_build_pfac(small, placement):
+    """A machine built without failure function and DFA scans with PFAC to the
+    oracle's list; DFA scans, batches and servers refuse it."""
+    w, expect = small
+    d, o = ac.patterns_csr(w.patterns)
+    a = ac.ac_build(d, o, opts=ac._opts(placement=placement, flags=ac.AC_BUILD_GOTO_ONLY,
+                                        hot_states=300 if placement == ac.AC_PLACE_LDS_HOT else 0))
+    assert ac.ac_info(a)["goto_only"] == 1
+    got = gpu_keys(a, w.text, algo=ac.AC_ALGO_PFAC)
+    assert np.array_equal(got, expect)
+    with pytest.raises(ac.AcError):
+        gpu_keys(a, w.text)  # DFA scan
+    with pytest.raises(ac.AcError):
+        ac.ac_batch_create([a], np.zeros(1, np.uint64), np.array([64], np.uint64), np.zeros(1, np.uint32))
+    with pytest.raises(ac.AcError):
+        ac.Server([a])

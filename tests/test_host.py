@@ -65,7 +65,8 @@ class Tables:
         self.info = ac.ac_info(a)
         self.C = self.info["n_cols"]
         self.S = self.info["n_states"]
-        self.dfa = ac.ac_get_table(a, ac.AC_TABLE_DFA).reshape(self.S, self.C)
+        dfa = ac.ac_get_table(a, ac.AC_TABLE_DFA)
+        self.dfa = dfa.reshape(self.S, self.C) if dfa.size else None  # None: goto-only build
         self.go = ac.ac_get_table(a, ac.AC_TABLE_GO).reshape(self.S, self.C)
         self.out_off = ac.ac_get_table(a, ac.AC_TABLE_OUT_OFF)
         self.out_ids = ac.ac_get_table(a, ac.AC_TABLE_OUT_IDS)
@@ -73,7 +74,8 @@ class Tables:
         self.own_ids = ac.ac_get_table(a, ac.AC_TABLE_OWN_IDS)
         self.cmap = ac.ac_get_table(a, ac.AC_TABLE_CMAP)
         H = self.info["hot_states"]
-        self.hot = ac.ac_get_table(a, ac.AC_TABLE_HOT_DFA)[: H * self.C].reshape(H, self.C)
+        hot = ac.ac_get_table(a, ac.AC_TABLE_HOT_DFA)
+        self.hot = hot[: H * self.C].reshape(H, self.C) if hot.size else None
         self.hot_go = ac.ac_get_table(a, ac.AC_TABLE_HOT_GO)[: H * self.C].reshape(H, self.C)
 
     def dfa_walk(self, text: bytes) -> np.ndarray:
@@ -231,3 +233,28 @@ def test_small_machine_image_is_complete():
         assert t.info["hot_states"] == int((~accept).sum()), pats
         assert t.info["placement"] == ac.AC_PLACE_LDS_HOT
         check_invariants(t, pats)
+
+
+@settings(max_examples=200, deadline=None)
+@given(case())
+def test_goto_only_build_walks_like_the_oracle(c):
+    """AC_BUILD_GOTO_ONLY keeps the goto function and the patterns ending at
+    each state (no failure function, no DFA): per-start-position walks over
+    it find exactly the oracle's matches, over the same trie as the full build."""
+    pats, text, hot = c
+    kw = dict(placement=ac.AC_PLACE_LDS_HOT, hot_states=hot) if hot else {}
+    t = Tables(build_host(pats, flags=ac.AC_BUILD_GOTO_ONLY, **kw))
+    assert t.dfa is None and t.info["goto_only"] == 1 and t.info["table_bytes"] == 0
+    assert t.info["n_states"] == ac.ac_info(build_host(pats))["n_states"]
+    assert np.array_equal(t.out_off, t.own_off) and np.array_equal(t.out_ids, t.own_ids)
+    assert np.array_equal(t.go_walks(text), oracle.oracle_match(text, pats))
+    H = t.info["hot_states"]
+    if H:
+        assert np.array_equal(t.hot_go.astype(np.uint32), t.go[:H] & 0x7FFFFFFF)
+        own = np.diff(t.own_off.astype(np.int64)) > 0
+        assert not own[:H].any()
+
+
+def test_goto_only_rejects_dfa_uses():
+    with pytest.raises(ac.AcError):
+        build_host([b"AB"], flags=2)  # unknown flag
