@@ -64,6 +64,10 @@ typedef struct {
     uint32_t lds_bytes;   /* LDS budget for the table image; 0 = 151 KiB (the rest of
                              the 160 KiB holds per-wave match queues) */
     uint32_t flags;       /* AC_BUILD_* bits */
+    uint32_t threads;     /* host threads for the construction (level by level in
+                             breadth-first order; the result does not depend on it);
+                             0 = hardware threads, at most 16 */
+    uint32_t reserved;
 } ac_build_opts;
 
 enum {

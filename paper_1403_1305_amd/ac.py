@@ -50,7 +50,8 @@ class AcError(RuntimeError):
 
 class ac_build_opts(ctypes.Structure):
     _fields_ = [("placement", ctypes.c_uint32), ("hot_states", ctypes.c_uint32),
-                ("lds_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("lds_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("threads", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ac_info_t(ctypes.Structure):
@@ -205,8 +206,8 @@ class Automaton:
         return ctypes.c_void_p(self.handle)
 
 
-def _opts(placement=AC_PLACE_AUTO, hot_states=0, lds_bytes=0, flags=0):
-    return ac_build_opts(placement, hot_states, lds_bytes, flags)
+def _opts(placement=AC_PLACE_AUTO, hot_states=0, lds_bytes=0, flags=0, threads=0):
+    return ac_build_opts(placement, hot_states, lds_bytes, flags, threads, 0)
 
 
 def ac_build(pat_bytes, pat_off, n_patterns: int | None = None, opts: ac_build_opts | None = None,

@@ -21,7 +21,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # no packed-FP32 instructions anywhere in the device code
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", f"-I{ROOT}/include"]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", f"-I{ROOT}/include"]
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", f"-I{ROOT}/include"]
 
 HIP_SOURCES = ["dfa_place_hot.hip", "dfa_place_full.hip", "dfa_place_global.hip", "dfa_batch_hot.hip",
                "dfa_batch_global.hip", "dfa.hip", "batch.hip", "serve.hip",

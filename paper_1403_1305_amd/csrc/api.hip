@@ -69,6 +69,7 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
         plan.only_if_needed = place == AC_PLACE_AUTO;
     }
     plan.goto_only = (flags & AC_BUILD_GOTO_ONLY) != 0;
+    plan.threads = opts ? opts->threads : 0u;
     std::string err;
     int rc;
     try {
@@ -76,6 +77,9 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
     } catch (const std::bad_alloc &) {
         rc = AC_ERR_NOMEM;
         err = "ac_build: out of host memory";
+    } catch (const std::exception &e) {  // e.g. a build thread that cannot start
+        rc = AC_ERR_NOMEM;
+        err = std::string("ac_build: ") + e.what();
     }
     if (rc != AC_OK) {
         delete a;

@@ -5,11 +5,36 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <thread>
 
 #include "../../include/ac.h"
 
 namespace acm {
 namespace {
+
+// f(begin, end) over [0, n) split into contiguous ranges, one per thread
+// (the caller's thread takes the first). Ranges are disjoint, so workers that
+// write only their own indices need no synchronisation.
+template <typename F>
+void parallel_for(uint32_t threads, size_t n, const F &f) {
+    constexpr size_t kGrain = 2048;
+    const size_t T = std::min<size_t>(std::max<uint32_t>(1, threads), (n + kGrain - 1) / kGrain);
+    if (T <= 1) {
+        f(size_t(0), n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    pool.reserve(T - 1);
+    for (size_t t = 1; t < T; ++t) pool.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+    f(size_t(0), n / T);
+    for (std::thread &th : pool) th.join();
+}
+
+uint32_t build_threads(uint32_t want) {
+    if (want) return std::min<uint32_t>(want, 64);
+    const uint32_t hw = std::thread::hardware_concurrency();
+    return std::max<uint32_t>(1, std::min<uint32_t>(hw ? hw : 1, 16));
+}
 
 uint32_t ceil_log2(uint32_t x) {
     uint32_t k = 0;
@@ -128,26 +153,53 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         return AC_ERR_TOO_LARGE;
     }
 
-    // ---- breadth-first order (children visited by column)
-    std::vector<uint32_t> order;
-    order.reserve(S);
-    std::vector<uint32_t> bfs(S);
-    order.push_back(0);
-    for (size_t i = 0; i < order.size(); ++i) {
-        uint32_t v = order[i];
-        bfs[v] = uint32_t(i);
-        for (uint32_t c = 0; c < C; ++c) {
-            int32_t w = kid[size_t(v) * C + c];
-            if (w >= 0) order.push_back(uint32_t(w));
+    // ---- breadth-first order (children visited by column), one level at a
+    // time: count each node's children, prefix-sum, then place them
+    const uint32_t NT = build_threads(plan.threads);
+    std::vector<uint32_t> order(S), bfs(S);
+    std::vector<uint32_t> level{0, 1};  // level d holds breadth-first ids [level[d], level[d+1])
+    order[0] = 0;
+    bfs[0] = 0;
+    {
+        std::vector<uint32_t> cnt;
+        size_t lo = 0, hi = 1;
+        while (lo < hi) {
+            const size_t nl = hi - lo;
+            cnt.assign(nl + 1, 0);
+            parallel_for(NT, nl, [&](size_t b, size_t e) {
+                for (size_t i = b; i < e; ++i) {
+                    const int32_t *row = &kid[size_t(order[lo + i]) * C];
+                    uint32_t k = 0;
+                    for (uint32_t c = 0; c < C; ++c) k += row[c] >= 0;
+                    cnt[i + 1] = k;
+                }
+            });
+            for (size_t i = 0; i < nl; ++i) cnt[i + 1] += cnt[i];
+            parallel_for(NT, nl, [&](size_t b, size_t e) {
+                for (size_t i = b; i < e; ++i) {
+                    const int32_t *row = &kid[size_t(order[lo + i]) * C];
+                    size_t q = hi + cnt[i];
+                    for (uint32_t c = 0; c < C; ++c)
+                        if (row[c] >= 0) {
+                            order[q] = uint32_t(row[c]);
+                            bfs[row[c]] = uint32_t(q);
+                            ++q;
+                        }
+                }
+            });
+            lo = hi;
+            hi += cnt[nl];
+            if (hi > lo) level.push_back(uint32_t(hi));
         }
     }
     // children in breadth-first ids
-    std::vector<int32_t> child(size_t(S) * C, -1);
-    for (uint32_t v = 0; v < S; ++v)
-        for (uint32_t c = 0; c < C; ++c) {
-            int32_t w = kid[size_t(v) * C + c];
-            if (w >= 0) child[size_t(bfs[v]) * C + c] = int32_t(bfs[w]);
+    std::vector<int32_t> child(size_t(S) * C);
+    parallel_for(NT, S, [&](size_t b, size_t e) {
+        for (size_t i = b; i < e; ++i) {
+            const int32_t *row = &kid[size_t(order[i]) * C];
+            for (uint32_t c = 0; c < C; ++c) child[i * C + c] = row[c] >= 0 ? int32_t(bfs[row[c]]) : -1;
         }
+    });
     std::vector<int32_t>().swap(kid);
 
     // ---- failure function and full DFA, row by row in breadth-first order.
@@ -162,18 +214,23 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         delta[c] = w >= 0 ? uint32_t(w) : 0u;
         if (w >= 0) fail[w] = 0;
     }
-    for (uint32_t b = 1; b < S && full; ++b) {
-        const uint32_t *frow = &delta[size_t(fail[b]) * C];
-        uint32_t *row = &delta[size_t(b) * C];
-        for (uint32_t c = 0; c < C; ++c) {
-            int32_t w = child[size_t(b) * C + c];
-            if (w >= 0) {
-                row[c] = uint32_t(w);
-                fail[w] = frow[c];
-            } else {
-                row[c] = frow[c];
+    // deeper levels in turn; the rows of one level only read shallower rows
+    for (size_t d = 1; full && d + 1 < level.size(); ++d) {
+        parallel_for(NT, level[d + 1] - level[d], [&](size_t b0, size_t e0) {
+            for (size_t b = level[d] + b0; b < level[d] + e0; ++b) {
+                const uint32_t *frow = &delta[size_t(fail[b]) * C];
+                uint32_t *row = &delta[b * C];
+                for (uint32_t c = 0; c < C; ++c) {
+                    const int32_t w = child[b * C + c];
+                    if (w >= 0) {
+                        row[c] = uint32_t(w);
+                        fail[w] = frow[c];
+                    } else {
+                        row[c] = frow[c];
+                    }
+                }
             }
-        }
+        });
     }
 
     // ---- output function: own patterns, plus the failure state's outputs
@@ -192,23 +249,34 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         out_off = own_off;
         out_ids = own_ids;
     } else {
-    out_ids.reserve(n);
-    for (uint32_t b = 0; b < S; ++b) {
-        out_off[b] = uint32_t(out_ids.size());
-        const uint32_t *o1 = &own_ids[own_off[b]], *e1 = &own_ids[own_off[b + 1]];
-        uint64_t fo = b ? out_off[fail[b]] : 0, fe = b ? out_off[fail[b] + 1] : 0;
-        if (out_ids.size() + (e1 - o1) + (fe - fo) >= (1ull << 32) - 1) {
-            err = "ac_build: output sets exceed 2^32 entries";
-            return AC_ERR_TOO_LARGE;
+        // a level at a time: sizes, offsets, then the merges (ascending ids)
+        out_off[1] = own_off[1] - own_off[0];
+        out_ids.assign(own_ids.begin() + own_off[0], own_ids.begin() + own_off[1]);
+        for (size_t d = 1; d + 1 < level.size(); ++d) {
+            const size_t lo = level[d], hi = level[d + 1];
+            parallel_for(NT, hi - lo, [&](size_t b0, size_t e0) {
+                for (size_t b = lo + b0; b < lo + e0; ++b)
+                    out_off[b + 1] = (own_off[b + 1] - own_off[b]) + (out_off[fail[b] + 1] - out_off[fail[b]]);
+            });
+            uint64_t at = out_off[lo];
+            for (size_t b = lo; b < hi; ++b) {
+                at += out_off[b + 1];
+                if (at >= (1ull << 32) - 1) {
+                    err = "ac_build: output sets exceed 2^32 entries";
+                    return AC_ERR_TOO_LARGE;
+                }
+                out_off[b + 1] = uint32_t(at);
+            }
+            out_ids.resize(at);
+            parallel_for(NT, hi - lo, [&](size_t b0, size_t e0) {
+                for (size_t b = lo + b0; b < lo + e0; ++b) {
+                    const uint32_t f = fail[b];
+                    std::merge(own_ids.begin() + own_off[b], own_ids.begin() + own_off[b + 1],
+                               out_ids.begin() + out_off[f], out_ids.begin() + out_off[f + 1],
+                               out_ids.begin() + out_off[b]);
+                }
+            });
         }
-        // merge two ascending lists; out(fail(b)) was finished earlier
-        size_t base = out_ids.size();
-        out_ids.resize(base + (e1 - o1) + (fe - fo));
-        std::merge(o1, e1, out_ids.begin() + fo, out_ids.begin() + fe, out_ids.begin() + base);
-        out_off[b + 1] = uint32_t(out_ids.size());
-    }
-    // out_off[b+1] of the last written state is also the final sentinel
-    out_off[S] = uint32_t(out_ids.size());
     }
     auto accepts = [&](uint32_t b) { return out_off[b + 1] > out_off[b]; };
 
@@ -311,22 +379,33 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     m.out_ids.reserve(out_ids.size());
     m.own_ids.clear();
     m.own_ids.reserve(n);
-    for (uint32_t f = 0; f < S; ++f) {
-        uint32_t b = inv[f];
-        for (uint32_t c = 0; c < C; ++c) {
-            if (full) {
-                const uint32_t t = delta[size_t(b) * C + c];
-                m.dfa[size_t(f) * C + c] = perm[t] | (accepts(t) ? kAccept : 0u);
+    parallel_for(NT, S, [&](size_t f0, size_t f1) {
+        for (size_t f = f0; f < f1; ++f) {
+            const uint32_t b = inv[f];
+            for (uint32_t c = 0; c < C; ++c) {
+                if (full) {
+                    const uint32_t t = delta[size_t(b) * C + c];
+                    m.dfa[f * C + c] = perm[t] | (accepts(t) ? kAccept : 0u);
+                }
+                const int32_t w = child[size_t(b) * C + c];
+                if (w >= 0) m.go[f * C + c] = perm[w] | (own_off[w + 1] > own_off[w] ? kAccept : 0u);
             }
-            int32_t w = child[size_t(b) * C + c];
-            if (w >= 0)
-                m.go[size_t(f) * C + c] = perm[w] | (own_off[w + 1] > own_off[w] ? kAccept : 0u);
         }
-        m.out_ids.insert(m.out_ids.end(), out_ids.begin() + out_off[b], out_ids.begin() + out_off[b + 1]);
-        m.out_off[f + 1] = uint32_t(m.out_ids.size());
-        m.own_ids.insert(m.own_ids.end(), own_ids.begin() + own_off[b], own_ids.begin() + own_off[b + 1]);
-        m.own_off[f + 1] = uint32_t(m.own_ids.size());
+    });
+    for (uint32_t f = 0; f < S; ++f) {
+        const uint32_t b = inv[f];
+        m.out_off[f + 1] = m.out_off[f] + (out_off[b + 1] - out_off[b]);
+        m.own_off[f + 1] = m.own_off[f] + (own_off[b + 1] - own_off[b]);
     }
+    m.out_ids.resize(out_ids.size());
+    m.own_ids.resize(n);
+    parallel_for(NT, S, [&](size_t f0, size_t f1) {
+        for (size_t f = f0; f < f1; ++f) {
+            const uint32_t b = inv[f];
+            std::copy(out_ids.begin() + out_off[b], out_ids.begin() + out_off[b + 1], m.out_ids.begin() + m.out_off[f]);
+            std::copy(own_ids.begin() + own_off[b], own_ids.begin() + own_off[b + 1], m.own_ids.begin() + m.own_off[f]);
+        }
+    });
     m.hot_states = H;
     m.hot_dfa.assign(full ? size_t(H) * C : 0, 0);
     m.hot_go.assign(size_t(H) * C, 0);

@@ -73,6 +73,7 @@ struct HotPlan {
     // failure function, no output unions, no full DFA (the failure-less machine
     // of Sec. II.B, all that the per-start-position matcher needs).
     bool goto_only = false;
+    uint32_t threads = 0;        // host threads for the build, 0 = hardware threads (at most 16)
 };
 
 // Returns 0 or a negative AC_ERR_* code with `err` set. Without an image,

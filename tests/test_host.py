@@ -258,3 +258,16 @@ def test_goto_only_build_walks_like_the_oracle(c):
 def test_goto_only_rejects_dfa_uses():
     with pytest.raises(ac.AcError):
         build_host([b"AB"], flags=2)  # unknown flag
+
+
+@pytest.mark.parametrize("flags", [0, ac.AC_BUILD_GOTO_ONLY])
+def test_threaded_build_is_identical(flags):
+    """The construction runs level by level on several threads; every table
+    must come out bit-identical to a one-thread build."""
+    w = plain_workload("dna256m", n=1 << 16)
+    pats = w.patterns[:6000]
+    one = build_host(pats, threads=1, flags=flags)
+    many = build_host(pats, threads=7, flags=flags)
+    for t in (ac.AC_TABLE_DFA, ac.AC_TABLE_GO, ac.AC_TABLE_OUT_OFF, ac.AC_TABLE_OUT_IDS, ac.AC_TABLE_OWN_OFF,
+              ac.AC_TABLE_OWN_IDS, ac.AC_TABLE_HOT_DFA, ac.AC_TABLE_HOT_GO, ac.AC_TABLE_CMAP):
+        assert np.array_equal(ac.ac_get_table(one, t), ac.ac_get_table(many, t)), t
