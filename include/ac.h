@@ -303,8 +303,20 @@ int ac_batch_info(const ac_batch *b, ac_batch_info_t *info);
 int ac_batch_scan(ac_batch *b, const uint8_t *d_texts, uint64_t *d_matches, uint64_t capacity,
                   uint64_t *d_count, int use_graph, void *stream);
 
-/* ac_batch_free -- release the plan and its graph. NULL is a no-op. */
+/* ac_batch_free -- release the plan and its graph; call it after the plan's
+ * last scan has completed. NULL is a no-op. */
 void ac_batch_free(ac_batch *b);
+
+/*
+ * ac_scan_batch -- one-shot form: plan, scan and free in one call, for texts
+ * packed one after another. Text t is bytes [text_off[t], text_off[t+1]) of
+ * d_texts (host array of n_texts + 1 offsets, each text start a multiple of
+ * 16) and is matched against autos[text_auto[t]]. Keys and overflow as
+ * ac_batch_scan. Synchronises `stream` before returning (the plan is freed).
+ */
+int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint8_t *d_texts,
+                  const uint64_t *text_off, const uint32_t *text_auto, uint32_t n_texts, uint64_t *d_matches,
+                  uint64_t capacity, uint64_t *d_count, const ac_batch_tune *tune, void *stream);
 
 /* ------------------------------------------------------------------ serving
  * A request loop over resident automata with continuous batching: requests
@@ -345,6 +357,10 @@ typedef struct {
     uint64_t submitted, completed, failed, queued, running, rescans;
     uint64_t pool_bytes, pool_used, pool_peak;
     uint64_t running_peak;  /* most requests on the device at once */
+    uint64_t bytes_done;    /* text bytes of successfully finished requests */
+    double p50_ms, p99_ms;  /* latency (arrival to completion) of the last finished
+                               requests, up to 65,536 of them; 0 if none */
+    double gbps;            /* bytes_done / (last completion - first arrival) */
 } ac_serve_stats_t;
 
 /*
@@ -355,6 +371,10 @@ typedef struct {
  */
 int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac_serve_opts *opts,
                     ac_server **out);
+
+/* ac_serve_add -- make one more automaton (built with ac_build on the
+ * server's device) resident; *id receives its index for ac_serve_submit. */
+int ac_serve_add(ac_server *s, const ac_automaton *a, uint32_t *id);
 
 /*
  * ac_serve_submit -- queue a scan of `text` (n bytes) with automaton

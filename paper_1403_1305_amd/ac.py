@@ -99,7 +99,8 @@ class ac_serve_result(ctypes.Structure):
 class ac_serve_stats_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "queued", "running",
                                                "rescans", "pool_bytes", "pool_used", "pool_peak",
-                                               "running_peak")]
+                                               "running_peak", "bytes_done")] + \
+               [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("gbps", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -127,7 +128,10 @@ SIGNATURES = {
     "ac_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ac_batch_info_t)]),
     "ac_batch_scan": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, ctypes.c_int, _vp]),
     "ac_batch_free": (None, [_vp]),
+    "ac_scan_batch": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _u64, _vp,
+                                     ctypes.POINTER(ac_batch_tune), _vp]),
     "ac_serve_create": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(ac_serve_opts), ctypes.POINTER(_vp)]),
+    "ac_serve_add": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_u32)]),
     "ac_serve_submit": (ctypes.c_int, [_vp, _u32, _vp, _u64, ctypes.c_int, _u64, ctypes.POINTER(_u64)]),
     "ac_serve_now_ns": (_u64, [_vp]),
     "ac_serve_wait": (ctypes.c_int, [_vp, _u64, ctypes.c_int64, ctypes.POINTER(ac_serve_result)]),
@@ -373,6 +377,13 @@ class Server:
                                               arrival_ns, ctypes.byref(t)))
         return t.value
 
+    def add(self, automaton: Automaton) -> int:
+        """Make another automaton resident; returns its index."""
+        i = _u32()
+        _check(load_library().ac_serve_add(self.handle, automaton.handle, ctypes.byref(i)))
+        self.autos.append(automaton)
+        return i.value
+
     def now_ns(self) -> int:
         return load_library().ac_serve_now_ns(self.handle)
 
@@ -413,6 +424,19 @@ class Server:
             self.handle = None
 
     __del__ = close
+
+
+def ac_scan_batch(autos, d_texts, text_off, text_auto, d_matches, capacity: int, d_count,
+                  tune: ac_batch_tune | None = None, stream=None) -> None:
+    """One-shot batch over texts packed back to back: text t is bytes
+    [text_off[t], text_off[t+1]) of d_texts (starts multiples of 16)."""
+    lib = load_library()
+    arr = (ctypes.c_void_p * len(autos))(*[a.handle for a in autos])
+    off = np.ascontiguousarray(text_off, dtype=np.uint64)
+    au = np.ascontiguousarray(text_auto, dtype=np.uint32)
+    _check(lib.ac_scan_batch(arr, len(autos), _ptr(d_texts), off.ctypes.data, au.ctypes.data, len(off) - 1,
+                             _ptr(d_matches), capacity, _ptr(d_count),
+                             ctypes.byref(tune) if tune is not None else None, _stream(stream)))
 
 
 def pack_texts(texts, align: int = 16) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

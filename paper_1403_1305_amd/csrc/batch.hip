@@ -327,4 +327,31 @@ void ac_batch_free(ac_batch *b) {
     delete b;
 }
 
+int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint8_t *d_texts,
+                  const uint64_t *text_off, const uint32_t *text_auto, uint32_t n_texts, uint64_t *d_matches,
+                  uint64_t capacity, uint64_t *d_count, const ac_batch_tune *tune, void *stream) {
+    if (n_texts > 0 && !text_off) return set_error(AC_ERR_INVALID, "ac_scan_batch: NULL text offsets");
+    std::vector<uint64_t> off, len;
+    try {
+        off.resize(n_texts);
+        len.resize(n_texts);
+    } catch (const std::bad_alloc &) {
+        return set_error(AC_ERR_NOMEM, "ac_scan_batch: out of host memory");
+    }
+    for (uint32_t t = 0; t < n_texts; ++t) {
+        if (text_off[t + 1] < text_off[t]) return set_error(AC_ERR_INVALID, "ac_scan_batch: decreasing text offsets");
+        off[t] = text_off[t];
+        len[t] = text_off[t + 1] - text_off[t];
+    }
+    ac_batch *b = nullptr;
+    int rc = ac_batch_create(autos, n_autos, off.data(), len.data(), text_auto, n_texts, tune, stream, &b);
+    if (rc != AC_OK) return rc;
+    rc = ac_batch_scan(b, d_texts, d_matches, capacity, d_count, 0, stream);
+    // the plan's device arrays must outlive the launch
+    const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    ac_batch_free(b);
+    if (rc != AC_OK) return rc;
+    return e == hipSuccess ? AC_OK : set_error(AC_ERR_HIP, std::string("ac_scan_batch: ") + hipGetErrorString(e));
+}
+
 }  // extern "C"

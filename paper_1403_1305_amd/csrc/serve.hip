@@ -40,6 +40,7 @@ constexpr uint64_t kNone = ~0ull;
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kPieceEvents = 8;   // copy -> scan hand-off events per slot, reused in turn
 constexpr uint32_t kMaxBypass = 16;    // later requests admitted ahead of a waiting head, at most
+constexpr size_t kLatencyRing = 65536;  // finished requests kept for the latency percentiles
 
 // First-fit allocator over one device allocation (offsets, 256-byte aligned).
 class DevicePool {
@@ -147,6 +148,7 @@ struct ac_server {
     int device = -1;
     std::vector<const ac_automaton *> autos;
     std::vector<double> rate;  // matches per text byte, per automaton
+    double rate0 = 0.0;        // the first guess, for automata added later
     uint64_t piece = 0;
     uint8_t *pool_base = nullptr;
     DevicePool pool;
@@ -160,6 +162,9 @@ struct ac_server {
     std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
     uint64_t next_id = 1;
     uint64_t submitted = 0, completed = 0, rescans = 0, failed = 0, running_peak = 0;
+    uint64_t bytes_done = 0, first_arrival = ~0ull, last_done = 0;
+    std::vector<uint64_t> latency;  // ring of the last kLatencyRing finished requests, ns
+    size_t latency_next = 0;
     bool stop = false;
     Clock::time_point t0;
     std::thread worker;
@@ -196,6 +201,17 @@ void finish(ac_server *s, Request *r, int status, const std::string &msg) {
     if (r->slot >= 0) {
         s->slots[size_t(r->slot)].req = nullptr;
         r->slot = -1;
+    }
+    if (status == AC_OK) {
+        s->bytes_done += r->n;
+        s->first_arrival = std::min(s->first_arrival, r->t_submit);
+        s->last_done = std::max(s->last_done, r->t_done);
+        const uint64_t lat = r->t_done - r->t_submit;
+        if (s->latency.size() < kLatencyRing)
+            s->latency.push_back(lat);
+        else
+            s->latency[s->latency_next] = lat;
+        s->latency_next = (s->latency_next + 1) % kLatencyRing;
     }
     ++s->completed;
     s->cv_done.notify_all();
@@ -453,6 +469,7 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     s->device = dev;
     s->autos.assign(autos, autos + n_autos);
     s->rate.assign(n_autos, rate);
+    s->rate0 = rate;
     s->piece = piece;
     s->t0 = Clock::now();
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s->pool_base), budget);
@@ -491,10 +508,20 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     return AC_OK;
 }
 
+int ac_serve_add(ac_server *s, const ac_automaton *a, uint32_t *id) {
+    if (!s || !a || !id) return set_error(AC_ERR_INVALID, "ac_serve_add: NULL argument");
+    if (!a->on_device || a->device != s->device || a->m.goto_only)
+        return set_error(AC_ERR_INVALID, "ac_serve_add: automaton is host-only, goto-only or on another device");
+    std::lock_guard<std::mutex> g(s->mu);
+    *id = uint32_t(s->autos.size());
+    s->autos.push_back(a);
+    s->rate.push_back(s->rate0);
+    return AC_OK;
+}
+
 int ac_serve_submit(ac_server *s, uint32_t automaton, const uint8_t *text, uint64_t n, int text_on_device,
                     uint64_t arrival_ns, uint64_t *ticket) {
     if (!s || !ticket) return set_error(AC_ERR_INVALID, "ac_serve_submit: NULL server or ticket");
-    if (automaton >= s->autos.size()) return set_error(AC_ERR_INVALID, "ac_serve_submit: no such automaton");
     if (n > 0 && !text) return set_error(AC_ERR_INVALID, "ac_serve_submit: NULL text");
     if (n >= (1ull << 32)) return set_error(AC_ERR_TOO_LARGE, "ac_serve_submit: text of 2^32 bytes or more");
     if (text_on_device && n > 0 && (reinterpret_cast<uintptr_t>(text) & 15u))
@@ -507,6 +534,7 @@ int ac_serve_submit(ac_server *s, uint32_t automaton, const uint8_t *text, uint6
     if (r->on_device) r->d_text = text;
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return set_error(AC_ERR_INVALID, "ac_serve_submit: server is shutting down");
+    if (automaton >= s->autos.size()) return set_error(AC_ERR_INVALID, "ac_serve_submit: no such automaton");
     const uint64_t need = (r->on_device ? 0 : ((n + kAlign - 1) & ~(kAlign - 1))) +
                           ((reservation(s, r.get()) * 8 + kAlign - 1) & ~(kAlign - 1));
     if (need > s->pool.size())
@@ -575,6 +603,18 @@ int ac_serve_stats(ac_server *s, ac_serve_stats_t *st) {
     st->pool_used = s->pool.used();
     st->pool_peak = s->pool.peak();
     st->running_peak = s->running_peak;
+    st->bytes_done = s->bytes_done;
+    st->p50_ms = st->p99_ms = st->gbps = 0.0;
+    if (!s->latency.empty()) {
+        std::vector<uint64_t> l(s->latency);
+        std::sort(l.begin(), l.end());
+        // nearest rank
+        auto pct = [&](double q) { return double(l[std::min(l.size() - 1, size_t(q * double(l.size())))]) * 1e-6; };
+        st->p50_ms = pct(0.50);
+        st->p99_ms = pct(0.99);
+    }
+    if (s->last_done > s->first_arrival)
+        st->gbps = double(s->bytes_done) / double(s->last_done - s->first_arrival);
     return AC_OK;
 }
 

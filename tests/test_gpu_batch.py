@@ -216,3 +216,22 @@ def test_batch_rejects_bad_plans():
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     with pytest.raises(ac.AcError):
         ac.ac_batch_scan(b, d[1:], out, 16, cnt)
+
+
+def test_one_shot_scan_batch(dna_batch):
+    """ac_scan_batch over texts packed back to back (CSR offsets) equals the
+    oracle, text by text."""
+    texts, sets, text_set, autos, _ = dna_batch
+    # pad each text to a multiple of 16 with a byte outside every pattern, so
+    # the packed texts are back to back and every start stays aligned
+    padded = [np.concatenate([t, np.full((-t.size) % 16, ord("N"), np.uint8)]) for t in texts]
+    off = np.concatenate([[0], np.cumsum([p.size for p in padded])]).astype(np.uint64)
+    buf = np.concatenate(padded) if padded else np.zeros(16, np.uint8)
+    expect = expected(padded, sets, text_set, off[:-1])
+    d = torch.from_numpy(buf).to("cuda")
+    cap = max(4096, 2 * buf.size)
+    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ac.ac_scan_batch(autos, d, off, text_set, out, cap, cnt)
+    n = int(cnt.item())
+    assert np.array_equal(np.sort(ac.keys_to_numpy(out[:n])), expect)

@@ -204,3 +204,21 @@ def test_scheduled_arrivals(setup):
         assert np.array_equal(np.sort(srv.keys(r)), expect[i])
         srv.release(t)
     srv.close()
+
+
+def test_add_automaton_and_latency_stats(setup):
+    """An automaton added to a running server serves requests; the stats
+    report latency percentiles and throughput over the finished requests."""
+    sets, autos, reqs, expect = setup
+    srv = ac.Server(autos[:1], piece_bytes=PIECE)
+    j = srv.add(autos[3])
+    assert j == 1
+    picks = [i for i, (a, t, _) in enumerate(reqs) if a in (0, 3) and t.size][:10]
+    keep, tickets = submit_all(srv, [((0 if reqs[i][0] == 0 else 1), reqs[i][1], reqs[i][2]) for i in picks])
+    got = collect(srv, tickets)
+    for g, i in zip(got, picks):
+        assert np.array_equal(g[0], expect[i]), i
+    st = srv.stats()
+    assert st["completed"] == len(picks) and st["bytes_done"] == sum(reqs[i][1].size for i in picks)
+    assert 0 < st["p50_ms"] <= st["p99_ms"] and st["gbps"] > 0
+    srv.close()
