@@ -382,3 +382,34 @@ def test_goto_only_build_pfac(small, placement):
         ac.ac_batch_create([a], np.zeros(1, np.uint64), np.array([64], np.uint64), np.zeros(1, np.uint32))
     with pytest.raises(ac.AcError):
         ac.Server([a])
+
+
+def test_scan_captured_in_a_graph(small):
+    """A caller can capture ac_scan (counter reset + scan, both kernels) into a
+    hipGraph and replay it; every replay, with eager work and host
+    synchronisation between replays, gives the oracle's list."""
+    w, expect = small
+    a = build(w.patterns)
+    d = to_device(w.text)
+    n = len(w.text)
+    cap = 1 << 16
+    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    opts = ac._scan_opts(ac.AC_ALGO_DFA)
+    s = torch.cuda.Stream()
+    ac.ac_scan(a, d, n, out, cap, cnt, opts, s)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ac.ac_scan(a, d, n, out, cap, cnt, opts, s)
+    other = to_device(dna_text(1 << 15, 9))
+    for i in range(4):
+        out.fill_(-1)
+        cnt.fill_(123456)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == expect.size, i
+        assert np.array_equal(np.sort(ac.keys_to_numpy(out[:expect.size])), expect), i
+        ac.scan_text(a, other)  # eager work between replays
+        torch.cuda.synchronize()
