@@ -179,7 +179,18 @@ uint64_t now_ns(const ac_server *s) {
 // Match-list keys reserved for a request: its length times the automaton's
 // learnt rate, with a quarter of headroom.
 uint64_t reservation(const ac_server *s, const Request *r) {
-    return uint64_t(double(r->n) * s->rate[r->automaton] * 1.25) + 1024;
+    const double keys = double(r->n) * s->rate[r->automaton] * 1.25 + 1024.0;
+    const uint64_t text = r->on_device ? 0 : (r->n + kAlign - 1) & ~(kAlign - 1);
+    const uint64_t room = s->pool.size() > text + kAlign ? (s->pool.size() - text - kAlign) / sizeof(uint64_t) : 0;
+    // never more than the pool could hold beside the text: a larger count
+    // is found by the rescan, which then needs exactly that much
+    return std::min<uint64_t>(keys < double(room) ? uint64_t(keys) : room, room);
+}
+
+// Bytes a request needs at once for its text copy and `keys` match keys.
+uint64_t footprint(const Request *r, uint64_t keys) {
+    const uint64_t text = r->on_device ? 0 : (r->n + kAlign - 1) & ~(kAlign - 1);
+    return text + ((std::max<uint64_t>(keys, 1) * sizeof(uint64_t) + kAlign - 1) & ~(kAlign - 1));
 }
 
 void finish(ac_server *s, Request *r, int status, const std::string &msg) {
@@ -357,6 +368,11 @@ void complete(ac_server *s, Request *r) {
 }
 
 bool retry_rescan(ac_server *s, Request *r) {
+    if (footprint(r, r->cap) > s->pool.size()) {
+        finish(s, r, AC_ERR_TOO_LARGE,
+               "the match list (" + std::to_string(r->cap) + " keys) does not fit the HBM budget");
+        return false;
+    }
     const uint64_t o = s->pool.alloc(r->cap * sizeof(uint64_t));
     if (o == kNone) return false;
     r->out_off = o;
@@ -407,9 +423,13 @@ void worker_main(ac_server *s) {
         const size_t queued = s->queue.size();
         admit(s);
         progress |= s->queue.size() != queued;
-        if (s->stop && s->running.empty()) {
+        bool on_device = false;  // some request has work queued on the GPU
+        for (const Request *r : s->running) on_device |= r->phase == Phase::Running;
+        if (s->stop && !on_device) {
             // shutting down with nothing on the device: whatever still waits
             // for memory can no longer get it
+            for (Request *r : s->running) finish(s, r, AC_ERR_BUSY, "server shut down during a rescan");
+            s->running.clear();
             for (Request *r : s->queue) finish(s, r, AC_ERR_BUSY, "server shut down before admission");
             s->queue.clear();
             break;
@@ -418,7 +438,7 @@ void worker_main(ac_server *s) {
         // sleep until a completion may have happened (poll), the next
         // scheduled arrival, or a submit / release / stop
         const uint64_t now = now_ns(s);
-        uint64_t wake = s->running.empty() ? kNone : now + 20000;
+        uint64_t wake = on_device ? now + 20000 : kNone;
         if (!s->queue.empty() && s->queue.front()->t_submit > now)
             wake = std::min(wake, s->queue.front()->t_submit);
         if (wake == kNone)
@@ -535,9 +555,7 @@ int ac_serve_submit(ac_server *s, uint32_t automaton, const uint8_t *text, uint6
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return set_error(AC_ERR_INVALID, "ac_serve_submit: server is shutting down");
     if (automaton >= s->autos.size()) return set_error(AC_ERR_INVALID, "ac_serve_submit: no such automaton");
-    const uint64_t need = (r->on_device ? 0 : ((n + kAlign - 1) & ~(kAlign - 1))) +
-                          ((reservation(s, r.get()) * 8 + kAlign - 1) & ~(kAlign - 1));
-    if (need > s->pool.size())
+    if (footprint(r.get(), 1024) > s->pool.size())
         return set_error(AC_ERR_TOO_LARGE, "ac_serve_submit: the request alone exceeds the HBM budget");
     r->id = s->next_id++;
     r->t_submit = std::max(arrival_ns, now_ns(s));
@@ -555,14 +573,21 @@ int ac_serve_submit(ac_server *s, uint32_t automaton, const uint8_t *text, uint6
 int ac_serve_wait(ac_server *s, uint64_t ticket, int64_t timeout_ms, ac_serve_result *res) {
     if (!s || !res) return set_error(AC_ERR_INVALID, "ac_serve_wait: NULL server or result");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->requests.find(ticket);
-    if (it == s->requests.end()) return set_error(AC_ERR_INVALID, "ac_serve_wait: unknown ticket");
-    Request *r = it->second.get();
-    auto done = [&] { return r->phase == Phase::Done; };
+    if (s->requests.find(ticket) == s->requests.end())
+        return set_error(AC_ERR_INVALID, "ac_serve_wait: unknown ticket");
+    // look the ticket up again after every wake-up: another thread may have
+    // released it meanwhile
+    auto done = [&] {
+        auto f = s->requests.find(ticket);
+        return f == s->requests.end() || f->second->phase == Phase::Done;
+    };
     if (timeout_ms < 0)
         s->cv_done.wait(lk, done);
     else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
         return set_error(AC_ERR_BUSY, "ac_serve_wait: request not finished within the timeout");
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(AC_ERR_INVALID, "ac_serve_wait: ticket released meanwhile");
+    Request *r = it->second.get();
     res->status = r->status;
     res->automaton = r->automaton;
     res->n = r->n;

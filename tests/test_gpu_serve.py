@@ -222,3 +222,34 @@ def test_add_automaton_and_latency_stats(setup):
     assert st["completed"] == len(picks) and st["bytes_done"] == sum(reqs[i][1].size for i in picks)
     assert 0 < st["p50_ms"] <= st["p99_ms"] and st["gbps"] > 0
     srv.close()
+
+
+def test_list_larger_than_budget_fails_cleanly():
+    """A request whose match list can never fit the budget ends with
+    AC_ERR_TOO_LARGE instead of waiting forever; the server stays usable."""
+    a = build([b"A"])  # a match at every 'A'
+    srv = ac.Server([a], hbm_budget=1 << 20, piece_bytes=1 << 16)
+    big = torch.full((600_000,), ord("A"), dtype=torch.uint8, device="cuda")  # 4.8 MB of keys
+    t = srv.submit(0, big, on_device=True)
+    with pytest.raises(ac.AcError) as e:
+        srv.wait(t)
+    assert e.value.status == ac.AC_ERR_TOO_LARGE
+    srv.release(t)
+    small = torch.full((1000,), ord("A"), dtype=torch.uint8, device="cuda")
+    t = srv.submit(0, small, on_device=True)
+    r = srv.wait(t)
+    assert r.n_matches == 1000
+    srv.release(t)
+    assert srv.stats()["pool_used"] == 0
+    srv.close()
+
+
+def test_close_while_waiting_for_memory():
+    """Results never released fill the pool; closing the server ends the
+    requests still waiting instead of hanging."""
+    a = build([b"A"])
+    srv = ac.Server([a], hbm_budget=1 << 20, piece_bytes=1 << 16, match_ppm=1_000_000)
+    x = torch.full((40_000,), ord("A"), dtype=torch.uint8, device="cuda")  # ~320 KB list each
+    tickets = [srv.submit(0, x, on_device=True) for _ in range(6)]
+    srv.wait(tickets[0])  # held, never released
+    srv.close()
