@@ -292,6 +292,8 @@ int ac_batch_scan(ac_batch *b, const uint8_t *d_texts, uint64_t *d_matches, uint
     if (!use_graph) return launch(b, d_texts, d_matches, capacity, d_count, s);
     if (!b->exec || b->g_text != d_texts || b->g_out != d_matches || b->g_cap != capacity ||
         b->g_count != d_count) {
+        // an earlier replay of the old graph may still run on the stream
+        if (b->exec) (void)hipStreamSynchronize(s);
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
