@@ -90,7 +90,14 @@ def cpu_baseline(w, sample_bytes, min_s=10.0, max_passes=3):
         ac_cpu.scan(sample)
         dt += time.perf_counter() - t0
         passes += 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(passes * len(sample) / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "host_threads": os.cpu_count(), "host_cpu": model,
             "sample": f"{passes} pass(es) over the first {len(sample) >> 20} MiB of the same text, full pattern "
                       f"set, single-threaded failure-link scan ({dt:.1f} s); build not timed"}
 
@@ -350,6 +357,7 @@ def main():
     p.add_argument("--no-batched", action="store_true", help="skip the batched sub-benchmark")
     p.add_argument("--no-served", action="store_true", help="skip the served sub-benchmark")
     p.add_argument("--no-build", action="store_true", help="skip the build-time sub-benchmark")
+    p.add_argument("--no-e1", action="store_true", help="skip the 0%%-planted timing check")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)
@@ -446,6 +454,8 @@ def main():
     algo_bytes = n + 8 * matches
     achieved = algo_bytes / (kernel_ms * 1e-3) / 1e9
 
+    kernel_ms_median = float(np.median(ms))
+
     # canonical order, timed separately
     keys = outs[:min(matches, cap)].clone()
     sort_ms = None
@@ -465,6 +475,29 @@ def main():
         pwall, pms = time_steps(pstep, max(3, args.steps // 4), stream, torch)
         pfac = {"value": round(n * len(pms) / pwall / 1e9, 3), "unit": "GB/s",
                 "kernel_ms": round(float(np.mean(pms)), 4), "matches": int(count.item())}
+
+    # measured streaming-read ceiling: a torch int64 sum over each text copy
+    def read_step(i):
+        copies[i % 3].view(torch.int64).sum()
+    for i in range(2):
+        read_step(i)
+    _, rms = time_steps(read_step, 6, stream, torch)
+    read_gbs = n / (float(np.median(rms)) * 1e-3) / 1e9
+
+    # planted patterns must not change the scan time (the same text, 0% planted)
+    e1 = None
+    if args.workload == "dna256m" and not args.no_e1:
+        w0 = plain_workload(args.workload, planted=0.0)
+        d0, o0 = ac.patterns_csr(w0.patterns)
+        a0 = ac.ac_build(d0, o0)
+        for i in range(2):
+            ac.ac_scan(a0, copies[i % 3], n, outs, cap, count, opts, stream)
+        _, ms0 = time_steps(lambda i: ac.ac_scan(a0, copies[i % 3], n, outs, cap, count, opts, stream),
+                            10, stream, torch)
+        e1 = {"planted": 0.0, "kernel_ms_median": round(float(np.median(ms0)), 4),
+              "matches": int(count.item()), "planted_10pct_kernel_ms_median": round(kernel_ms_median, 4),
+              "ratio": round(float(np.median(ms0)) / kernel_ms_median, 3)}
+        del a0
 
     if args.calib_copy:
         dst = torch.empty_like(copies[0])
@@ -509,6 +542,11 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": profiled_traffic(args.workload)},
         "kernel_ms": round(kernel_ms, 4),
+        "kernel_ms_median": round(kernel_ms_median, 4),
+        "hbm_read_ceiling": {"value": round(read_gbs, 1), "unit": "GB/s",
+                             "how": "median torch int64 sum over the same 256 MiB text copies",
+                             "scan_frac": round(value / read_gbs, 4)},
+        "e1_planted0": e1,
         "build_ms": round(info["build_ms"], 2),
         "build_upload_ms": round(build_wall_ms, 2),
         "sort_ms": sort_ms,
