@@ -241,7 +241,8 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     torch.cuda.empty_cache()
 
     budget = 4 << 30
-    srv = ac.Server(autos, hbm_budget=budget, max_inflight=8)
+    srv = ac.Server(autos, hbm_budget=budget, max_inflight=args.slots,
+                    flags=ac.AC_SERVE_MERGED if args.serve_merged else 0)
 
     def replay(arrivals_ns):
         base = srv.now_ns() + 50_000_000  # submissions finish well before the first arrival
@@ -249,7 +250,7 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
                               arrival_ns=base + int(arrivals_ns[i])) for i in range(R)]
         res = []
         for t in tickets:
-            r = srv.wait(t)
+            r = srv.wait(t, 120_000)  # an error, not a silent hang, if a request never finishes
             res.append((r.t_submit_ns, r.t_admit_ns, r.t_done_ns, r.n_matches, r.rescans))
             srv.release(t)
         a = np.array(res, dtype=np.float64)
@@ -282,7 +283,7 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     sample = np.argsort(w.length)[:: max(1, R // 12)]
     for i in sample:
         t = srv.submit(int(w.automaton[i]), views[i], n=int(w.length[i]), on_device=True)
-        r = srv.wait(t)
+        r = srv.wait(t, 120_000)
         a = np.sort(srv.keys(r))
         srv.release(t)
         b = np.sort(ac.keys_to_numpy(ac.scan_text(autos[int(w.automaton[i])], views[i])))
@@ -291,7 +292,8 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     srv.close()
     return {
         "workload": f"served: {SERVED_DESC}", "requests": R, "text_bytes": total, "automata": len(autos),
-        "slots": 8, "hbm_budget": budget, "piece_bytes": 16 << 20,
+        "slots": args.slots, "hbm_budget": budget, "piece_bytes": 16 << 20,
+        "merged": bool(args.serve_merged), "merged_launches": st["merged_launches"],
         "serial_plain": {"value": round(serial_gbs, 3), "unit": "GB/s", "ms": round(serial_ms, 3)},
         "saturated": sat, "poisson": poisson,
         "exact_vs_plain": exact, "pool_peak": st["pool_peak"], "build_s": round(build_s, 2),
@@ -358,6 +360,9 @@ def main():
     p.add_argument("--no-served", action="store_true", help="skip the served sub-benchmark")
     p.add_argument("--no-build", action="store_true", help="skip the build-time sub-benchmark")
     p.add_argument("--no-e1", action="store_true", help="skip the 0%%-planted timing check")
+    p.add_argument("--slots", type=int, default=8, help="requests a server holds on the device at once")
+    p.add_argument("--serve-merged", action="store_true",
+                   help="served form: scan requests admitted together in shared launches (experimental)")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)

@@ -336,8 +336,17 @@ typedef struct {
     uint32_t match_ppm;    /* first guess of matches per million text bytes, used to
                               size match lists until finished requests refine it;
                               0 = 20000. A low guess costs a rescan, never a result. */
-    uint32_t reserved;
+    uint32_t flags;        /* AC_SERVE_* bits */
 } ac_serve_opts;
+
+enum {
+    /* Experimental: requests of one kernel shape (LDS image or not,
+     * byte-class scheme) admitted together, each shorter than 64 MiB, are
+     * scanned in one shared launch and their keys handed out to the requests
+     * afterwards. By default every request scans on its own slot's stream,
+     * in pieces. */
+    AC_SERVE_MERGED = 2
+};
 
 typedef struct {
     int32_t status;           /* AC_OK or the error that ended the request */
@@ -357,6 +366,7 @@ typedef struct {
     uint64_t submitted, completed, failed, queued, running, rescans;
     uint64_t pool_bytes, pool_used, pool_peak;
     uint64_t running_peak;  /* most requests on the device at once */
+    uint64_t merged_launches; /* shared launches issued */
     uint64_t bytes_done;    /* text bytes of successfully finished requests */
     double p50_ms, p99_ms;  /* latency (arrival to completion) of the last finished
                                requests, up to 65,536 of them; 0 if none */

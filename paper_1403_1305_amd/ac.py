@@ -34,6 +34,7 @@ AC_ALGO_DFA = 0
 AC_ALGO_PFAC = 1
 
 AC_BUILD_GOTO_ONLY = 1
+AC_SERVE_MERGED = 2
 
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
     AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP = range(9)
@@ -86,7 +87,7 @@ class ac_batch_info_t(ctypes.Structure):
 class ac_serve_opts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("piece_bytes", ctypes.c_uint32), ("match_ppm", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32)]
 
 
 class ac_serve_result(ctypes.Structure):
@@ -99,7 +100,7 @@ class ac_serve_result(ctypes.Structure):
 class ac_serve_stats_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "queued", "running",
                                                "rescans", "pool_bytes", "pool_used", "pool_peak",
-                                               "running_peak", "bytes_done")] + \
+                                               "running_peak", "merged_launches", "bytes_done")] + \
                [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("gbps", ctypes.c_double)]
 
 
@@ -352,11 +353,11 @@ class Server:
     """Owning handle of an ac_server* (keeps its automata alive)."""
 
     def __init__(self, autos, hbm_budget: int = 0, max_inflight: int = 0, piece_bytes: int = 0,
-                 match_ppm: int = 0):
+                 match_ppm: int = 0, flags: int = 0):
         lib = load_library()
         self.autos = list(autos)
         arr = (ctypes.c_void_p * len(self.autos))(*[a.handle for a in self.autos])
-        o = ac_serve_opts(hbm_budget, max_inflight, piece_bytes, match_ppm, 0)
+        o = ac_serve_opts(hbm_budget, max_inflight, piece_bytes, match_ppm, flags)
         h = _vp()
         _check(lib.ac_serve_create(arr, len(self.autos), ctypes.byref(o), ctypes.byref(h)))
         self.handle = h.value

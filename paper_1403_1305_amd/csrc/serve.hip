@@ -9,6 +9,15 @@
 // of the paper's Alg. 1), so a long request never occupies the whole device
 // in one launch and host texts can be copied in while earlier pieces scan.
 //
+// With AC_SERVE_MERGED, requests of the same kernel shape admitted together
+// are scanned together:
+// one launch of the served kernel covers all their texts (chunks of every
+// request in one work list, tasks taken from a device counter), its keys
+// carry the request's slot, and a second kernel hands each key to its
+// request's list. That keeps the device busy when requests are too short to
+// fill it alone. Requests of 64 MiB or more, and reruns, use the per-request
+// path above.
+//
 // The match list is sized before the count is known: the reservation is the
 // text length times a per-automaton match rate learnt from finished requests.
 // A request whose count exceeds its reservation is scanned again into a list
@@ -30,6 +39,8 @@
 #include <vector>
 
 #include "automaton.h"
+#include "device_common.h"
+#include "dfa_kernel.h"
 #include "scan.h"
 
 namespace {
@@ -41,6 +52,68 @@ constexpr uint64_t kAlign = 256;
 constexpr uint32_t kPieceEvents = 8;   // copy -> scan hand-off events per slot, reused in turn
 constexpr uint32_t kMaxBypass = 16;    // later requests admitted ahead of a waiting head, at most
 constexpr size_t kLatencyRing = 65536;  // finished requests kept for the latency percentiles
+constexpr uint32_t kLaunches = 3;          // merged launches in flight at once
+constexpr uint32_t kMaxTasks = 1u << 16;   // served tasks per merged launch
+constexpr uint64_t kLaunchBytes = 512ull << 20;  // text bytes per merged launch (a larger request goes alone)
+constexpr uint32_t kMaxAutos = 256;        // automata a server holds
+constexpr uint32_t kMaxSlots = 1u << (32 - acm::dfa::kSlotShift);
+
+// Where the demultiplexing kernel puts the keys of one slot.
+struct DemuxSlot {
+    uint64_t *list;
+    uint64_t cap;
+    unsigned long long *count;
+    uint64_t used;  // nonzero: the slot's request is in the launch
+};
+
+// Zero the launch's key count and task counter and the counts of its requests.
+__global__ void merged_prepare_kernel(unsigned long long *launch_count, uint32_t *next_task,
+                                      const DemuxSlot *slots) {
+    const uint32_t i = threadIdx.x;
+    if (i == 0) {
+        *launch_count = 0;
+        *next_task = 0;
+    }
+    if (i < kMaxSlots && slots[i].used) *slots[i].count = 0;
+}
+
+// Hand every key of the launch's list to its request: the slot is the top of
+// the position field, the rest is the end position within the request. A
+// wave takes 64 keys at a time and, for each slot among them, reserves room
+// with one atomic and places its keys by their rank (keys of one request
+// mostly arrive together, so that is usually a single atomic per wave).
+__global__ void merged_demux_kernel(const uint64_t *keys, const unsigned long long *n_keys, uint64_t cap,
+                                    const DemuxSlot *slots) {
+    const uint64_t n = min(uint64_t(*n_keys), cap);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    // whole waves step together, so every ballot sees all 64 lanes
+    for (uint64_t base = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const uint64_t i = base + lane;
+        const bool has = i < n;
+        const uint64_t k = has ? keys[i] : 0ull;
+        const uint32_t pos = uint32_t(k >> 32);
+        const uint32_t slot = pos >> acm::dfa::kSlotShift;
+        uint64_t todo = __ballot(has);
+        while (todo) {
+            const uint32_t leader = uint32_t(__ffsll((unsigned long long)todo) - 1);
+            const uint32_t lslot = __shfl(slot, int(leader));
+            const bool mine = has && slot == lslot;
+            const uint64_t same = __ballot(mine);
+            const DemuxSlot d = slots[lslot];
+            unsigned long long first = 0;
+            if (lane == leader) first = atomicAdd(d.count, (unsigned long long)__popcll(same));
+            first = __shfl(first, int(leader));
+            if (mine) {
+                const uint64_t at = first + acm::lane_rank(same);
+                const uint64_t end = pos & ((1u << acm::dfa::kSlotShift) - 1u);
+                if (at < d.cap) d.list[at] = (end << 32) | (k & 0xffffffffull);
+            }
+            todo &= ~same;
+        }
+    }
+}
+
 
 // First-fit allocator over one device allocation (offsets, 256-byte aligned).
 class DevicePool {
@@ -127,6 +200,8 @@ struct Request {
     uint64_t *d_out = nullptr;
     uint64_t n_matches = 0;
     uint32_t pieces = 0, rescans = 0, bypassed = 0;
+    bool merged = false;    // scanned in a merged launch (else on its slot's stream)
+    bool launched = false;  // merged: in a launch
     int status = AC_OK;
     std::string message;
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
@@ -142,6 +217,21 @@ struct Slot {
     Request *req = nullptr;
 };
 
+// One launch of the served kernel over several requests.
+struct MergedLaunch {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    acm::dfa::ServedTask *h_tasks = nullptr, *d_tasks = nullptr;  // pinned staging, device copy
+    DemuxSlot *h_demux = nullptr, *d_demux = nullptr;
+    unsigned long long *d_count = nullptr;  // keys of the launch
+    uint32_t *d_next = nullptr;             // task counter
+    uint64_t *h_count = nullptr;            // pinned: the launch's key count
+    uint64_t *h_words = nullptr;            // pinned mirror of every slot's device words
+    uint64_t out_off = kNone, out_cap = 0;
+    std::vector<Request *> reqs;
+    bool busy = false;
+};
+
 }  // namespace
 
 struct ac_server {
@@ -153,6 +243,10 @@ struct ac_server {
     uint8_t *pool_base = nullptr;
     DevicePool pool;
     std::vector<Slot> slots;
+    std::vector<MergedLaunch> launches;
+    acm::dfa::DfaArgs *d_autos = nullptr;  // every automaton's tables, for the served kernel
+    bool merge = false;
+    uint64_t merged_launches = 0;
     void *words = nullptr;       // device words of every slot
     uint64_t *h_counts = nullptr;  // pinned count words of every slot
     std::mutex mu;
@@ -292,12 +386,43 @@ bool reserve(ac_server *s, Request *r) {
     return true;
 }
 
+// The request can join merged launches: its end positions fit below the
+// slot field and its slot fits the field.
+bool mergeable(const ac_server *s, const Request *r) {
+    return s->merge && r->n < (1ull << acm::dfa::kSlotShift) && uint32_t(r->slot) < kMaxSlots &&
+           s->autos[r->automaton]->m.m_max < (1u << 20);
+}
+
 void start(ac_server *s, Request *r, int slot) {
     r->slot = slot;
     s->slots[size_t(slot)].req = r;
     r->phase = Phase::Running;
     r->t_admit = now_ns(s);
     std::string err;
+    if (mergeable(s, r)) {
+        // the text goes to the device at once; the next merged launch waits for it
+        r->merged = true;
+        r->launched = false;
+        r->pieces = 1;
+        int rc = AC_OK;
+        if (!r->on_device) {
+            Slot &sl = s->slots[size_t(slot)];
+            hipError_t e = hipMemcpyAsync(const_cast<uint8_t *>(r->d_text), r->src, r->n, hipMemcpyHostToDevice, sl.copy);
+            if (e == hipSuccess) e = hipEventRecord(sl.piece[0], sl.copy);
+            if (e != hipSuccess) {
+                rc = AC_ERR_HIP;
+                err = std::string("text copy: ") + hipGetErrorString(e);
+            }
+        }
+        if (rc != AC_OK) {
+            (void)hipStreamSynchronize(s->slots[size_t(slot)].copy);
+            finish(s, r, rc, err);
+        } else {
+            s->running.push_back(r);
+            s->running_peak = std::max<uint64_t>(s->running_peak, s->running.size());
+        }
+        return;
+    }
     const int rc = issue(s, r, !r->on_device, err);
     if (rc != AC_OK) {
         // nothing after the failing call was queued; let the slot drain first
@@ -388,6 +513,199 @@ bool retry_rescan(ac_server *s, Request *r) {
     return true;
 }
 
+// A request admitted for merging scans on its own slot's stream instead (its
+// text is on the device, or being copied there on the slot's copy stream).
+void go_alone(ac_server *s, Request *r) {
+    r->merged = false;
+    Slot &sl = s->slots[size_t(r->slot)];
+    std::string err;
+    const hipError_t e = r->on_device ? hipSuccess : hipStreamWaitEvent(sl.scan, sl.piece[0], 0);
+    const int rc = e == hipSuccess ? issue(s, r, false, err) : AC_ERR_HIP;
+    if (rc != AC_OK) {
+        (void)hipStreamSynchronize(sl.scan);
+        finish(s, r, rc, err.empty() ? std::string("text copy wait failed") : err);
+    }
+}
+
+// Kernel shape of a request's automaton: LDS image or global table, and
+// the byte-class scheme (all requests of one merged launch share it).
+uint64_t shape_of(const ac_server *s, const Request *r) {
+    const acm::Machine &m = s->autos[r->automaton]->m;
+    const uint64_t hot = m.hot_states > 0 ? 1 : 0;
+    return hot << 40 | uint64_t(m.hashed ? 1 : 0) << 32 | (m.hashed ? m.log2_cols : 0xffu);
+}
+
+// Form and queue one merged launch on an idle launch slot, from requests
+// waiting for one (in admission order, one kernel shape). False if none.
+bool merge_one(ac_server *s, MergedLaunch &L) {
+    std::vector<Request *> cand;
+    for (Request *r : s->running)
+        if (r->merged && !r->launched && r->phase == Phase::Running) cand.push_back(r);
+    if (cand.empty()) return false;
+    const uint64_t shape = shape_of(s, cand.front());
+    std::vector<Request *> pick;
+    uint64_t bytes = 0;
+    for (Request *r : cand) {
+        if (shape_of(s, r) != shape) continue;
+        if (!pick.empty() && bytes + r->n > kLaunchBytes) continue;
+        pick.push_back(r);
+        bytes += r->n;
+    }
+    const acm::Machine &m0 = s->autos[pick.front()->automaton]->m;
+    const bool hot = m0.hot_states > 0;
+    const uint32_t K = 1u, bb = 128u;  // one walker per lane: the served kernels spill with two
+    const uint32_t block = hot ? 1024u : 256u;
+    const int l2 = m0.hashed ? int(m0.log2_cols) : -1;
+    acm::dfa::ServedKernel kernel = hot ? acm::dfa::select_served_hot(m0.hashed, l2, K, bb)
+                                        : acm::dfa::select_served_global(m0.hashed, l2, K, bb);
+    if (!kernel) {  // no such kernel: these requests go their own way
+        for (Request *r : pick) go_alone(s, r);
+        return true;
+    }
+    uint32_t image = 0;
+    for (Request *r : pick)
+        if (hot) image = std::max<uint32_t>(image, (s->autos[r->automaton]->m.hot_states *
+                                                    s->autos[r->automaton]->m.n_cols * 2u + 15u) & ~15u);
+    const uint32_t lds = (block / 64) * acm::kQueueBytesPerWave + 256 + image;
+    const uint64_t grid_max =
+        uint64_t(acm::compute_units(s->device)) * uint64_t(acm::occupancy(reinterpret_cast<const void *>(kernel), block, lds));
+    const uint64_t walkers = grid_max * block * K;
+    const uint64_t per_task = uint64_t(block) * K;
+    // chunks: one per walker the chip holds over the whole launch, as for a
+    // plain scan of that many bytes; lengthened if the task list would not fit
+    uint32_t n_tasks = 0;
+    uint64_t out_cap = 0;
+    auto plan = [&](const std::vector<Request *> &reqs) {
+        uint64_t total = 0;
+        for (Request *r : reqs) total += r->n;
+        uint64_t fill = std::max<uint64_t>(1, (total + walkers - 1) / walkers);
+        while (true) {
+            n_tasks = 0;
+            out_cap = 0;
+            for (Request *r : reqs) {
+                const uint32_t mm = s->autos[r->automaton]->m.m_max;
+                uint64_t chunk = fill >= 4ull * mm ? (fill + bb - 1) & ~uint64_t(bb - 1)
+                                                   : std::max<uint64_t>(16, (fill + 15) & ~uint64_t(15));
+                chunk = std::min<uint64_t>(chunk, 1u << 30);
+                const uint64_t items = (r->n + chunk - 1) / chunk;
+                for (uint64_t i0 = 0; i0 < items; i0 += per_task) {
+                    if (n_tasks < kMaxTasks) {
+                        acm::dfa::ServedTask &t = L.h_tasks[n_tasks];
+                        t.text = r->d_text;
+                        t.own_first = uint32_t(i0 * chunk);
+                        t.n_items = uint32_t(std::min<uint64_t>(per_task, items - i0));
+                        t.chunk = uint32_t(chunk);
+                        t.text_len = uint32_t(r->n);
+                        t.automaton = r->automaton;
+                        t.slot = uint32_t(r->slot);
+                    }
+                    ++n_tasks;
+                }
+                out_cap += std::max<uint64_t>(1, r->cap);
+            }
+            if (n_tasks <= kMaxTasks) return;
+            fill *= 2;
+        }
+    };
+    plan(pick);
+    uint64_t out_off = s->pool.alloc(out_cap * sizeof(uint64_t));
+    if (out_off == kNone && pick.size() > 1) {
+        pick.resize(1);
+        plan(pick);
+        out_off = s->pool.alloc(out_cap * sizeof(uint64_t));
+    }
+    if (out_off == kNone) {
+        // no room for a launch list beside the requests' own lists: the first
+        // request scans on its own stream, which needs only its own list
+        go_alone(s, pick.front());
+        return true;
+    }
+    for (uint32_t i = 0; i < kMaxSlots; ++i) L.h_demux[i] = DemuxSlot{nullptr, 0, nullptr, 0};
+    for (Request *r : pick) {
+        Slot &sl = s->slots[size_t(r->slot)];
+        L.h_demux[r->slot] = DemuxSlot{r->d_out, r->cap, reinterpret_cast<unsigned long long *>(sl.d_count), 1};
+    }
+    uint64_t *d_out = reinterpret_cast<uint64_t *>(s->pool_base + out_off);
+    std::string err;
+    hipError_t e = hipSuccess;
+    for (Request *r : pick)
+        if (!r->on_device && e == hipSuccess) e = hipStreamWaitEvent(L.stream, s->slots[size_t(r->slot)].piece[0], 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L.d_tasks, L.h_tasks, size_t(n_tasks) * sizeof(acm::dfa::ServedTask), hipMemcpyHostToDevice,
+                           L.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L.d_demux, L.h_demux, kMaxSlots * sizeof(DemuxSlot), hipMemcpyHostToDevice, L.stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(merged_prepare_kernel, dim3(1), dim3(kMaxSlots), 0, L.stream, L.d_count, L.d_next,
+                           L.d_demux);
+        e = hipGetLastError();
+    }
+    int rc = e == hipSuccess ? AC_OK : AC_ERR_HIP;
+    if (rc == AC_OK) {
+        acm::dfa::ServedArgs args{L.d_tasks, n_tasks, s->d_autos, d_out, out_cap, L.d_count, L.d_next};
+        const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(grid_max, n_tasks)));
+        rc = acm::launch_kernel(kernel, grid, block, lds, L.stream, args, err);
+    }
+    if (rc == AC_OK) {
+        hipLaunchKernelGGL(merged_demux_kernel, dim3(512), dim3(256), 0, L.stream, d_out, L.d_count, out_cap,
+                           L.d_demux);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(L.h_count, L.d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, L.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(L.h_words, s->words, s->slots.size() * 16, hipMemcpyDeviceToHost, L.stream);
+        if (e == hipSuccess) e = hipEventRecord(L.done, L.stream);
+        if (e != hipSuccess) {
+            rc = AC_ERR_HIP;
+            err = std::string("merged launch: ") + hipGetErrorString(e);
+        }
+    }
+    if (rc != AC_OK) {
+        (void)hipStreamSynchronize(L.stream);
+        s->pool.release(out_off);
+        for (Request *r : pick) finish(s, r, rc, err.empty() ? std::string("merged launch failed") : err);
+        return true;
+    }
+    for (Request *r : pick) r->launched = true;
+    L.reqs = pick;
+    L.out_off = out_off;
+    L.out_cap = out_cap;
+    L.busy = true;
+    ++s->merged_launches;
+    return true;
+}
+
+// A merged launch has finished: settle each of its requests.
+void settle_launch(ac_server *s, MergedLaunch &L) {
+    const bool overflow = *L.h_count > L.out_cap;
+    for (Request *r : L.reqs) {
+        r->merged = false;  // from here on any rerun uses its slot's stream
+        if (overflow) {
+            // the launch's list was too short: keys are missing, so scan again
+            // on the request's own stream (its text is on the device)
+            std::string err;
+            const int rc = issue(s, r, false, err);
+            if (rc != AC_OK) {
+                (void)hipStreamSynchronize(s->slots[size_t(r->slot)].scan);
+                finish(s, r, rc, err);
+            } else {
+                ++r->rescans;
+                ++s->rescans;
+            }
+            continue;
+        }
+        Slot &sl = s->slots[size_t(r->slot)];
+        *sl.h_count = L.h_words[size_t(r->slot) * 2];
+        complete(s, r);
+        if (r->phase == Phase::WaitMemory) retry_rescan(s, r);
+    }
+    s->pool.release(L.out_off);
+    L.out_off = kNone;
+    L.out_cap = 0;
+    L.reqs.clear();
+    L.busy = false;
+}
+
 void worker_main(ac_server *s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -396,7 +714,9 @@ void worker_main(ac_server *s) {
         for (size_t i = 0; i < s->running.size();) {
             Request *r = s->running[i];
             bool drop = false;
-            if (r->phase == Phase::Running) {
+            if (r->merged) {
+                drop = r->phase == Phase::Done;  // settled by its launch
+            } else if (r->phase == Phase::Running) {
                 const hipError_t q = hipEventQuery(s->slots[size_t(r->slot)].done);
                 if (q == hipSuccess) {
                     complete(s, r);
@@ -420,15 +740,39 @@ void worker_main(ac_server *s) {
                 ++i;
             }
         }
+        for (MergedLaunch &L : s->launches)
+            if (L.busy) {
+                const hipError_t q = hipEventQuery(L.done);
+                if (q == hipSuccess) {
+                    settle_launch(s, L);
+                    progress = true;
+                } else if (q != hipErrorNotReady) {
+                    for (Request *r : L.reqs) finish(s, r, AC_ERR_HIP, std::string("merged launch: ") + hipGetErrorString(q));
+                    s->pool.release(L.out_off);
+                    L.reqs.clear();
+                    L.busy = false;
+                    progress = true;
+                }
+            }
+        // drop requests their launches finished
+        s->running.erase(std::remove_if(s->running.begin(), s->running.end(),
+                                        [](const Request *r) { return r->phase == Phase::Done; }),
+                         s->running.end());
         const size_t queued = s->queue.size();
         admit(s);
         progress |= s->queue.size() != queued;
+        for (MergedLaunch &L : s->launches)
+            if (!L.busy && merge_one(s, L)) progress = true;
+        s->running.erase(std::remove_if(s->running.begin(), s->running.end(),
+                                        [](const Request *r) { return r->phase == Phase::Done; }),
+                         s->running.end());
         bool on_device = false;  // some request has work queued on the GPU
-        for (const Request *r : s->running) on_device |= r->phase == Phase::Running;
+        for (const Request *r : s->running) on_device |= r->phase == Phase::Running && !(r->merged && !r->launched);
+        for (const MergedLaunch &L : s->launches) on_device |= L.busy;
         if (s->stop && !on_device) {
             // shutting down with nothing on the device: whatever still waits
             // for memory can no longer get it
-            for (Request *r : s->running) finish(s, r, AC_ERR_BUSY, "server shut down during a rescan");
+            for (Request *r : s->running) finish(s, r, AC_ERR_BUSY, "server shut down before the request could run");
             s->running.clear();
             for (Request *r : s->queue) finish(s, r, AC_ERR_BUSY, "server shut down before admission");
             s->queue.clear();
@@ -456,10 +800,29 @@ void destroy(ac_server *s) {
         for (hipEvent_t &e : sl.piece)
             if (e) (void)hipEventDestroy(e);
     }
+    for (MergedLaunch &L : s->launches) {
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.h_tasks) (void)hipHostFree(L.h_tasks);
+        if (L.d_tasks) (void)hipFree(L.d_tasks);
+        if (L.h_demux) (void)hipHostFree(L.h_demux);
+        if (L.d_demux) (void)hipFree(L.d_demux);
+        if (L.d_count) (void)hipFree(L.d_count);
+        if (L.h_count) (void)hipHostFree(L.h_count);
+        if (L.h_words) (void)hipHostFree(L.h_words);
+    }
+    if (s->d_autos) (void)hipFree(s->d_autos);
     if (s->words) (void)hipFree(s->words);
     if (s->h_counts) (void)hipHostFree(s->h_counts);
     if (s->pool_base) (void)hipFree(s->pool_base);
     delete s;
+}
+
+// Upload automaton i's tables to the served kernel's array.
+hipError_t upload_auto(ac_server *s, uint32_t i) {
+    acm::dfa::DfaArgs a{};
+    acm::dfa::fill_machine_args(s->autos[i]->dm, a);
+    return hipMemcpy(s->d_autos + i, &a, sizeof(a), hipMemcpyHostToDevice);
 }
 
 }  // namespace
@@ -482,7 +845,10 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     const uint64_t piece = opts && opts->piece_bytes ? opts->piece_bytes : (16u << 20);
     const double rate = (opts && opts->match_ppm ? opts->match_ppm : 20000u) * 1e-6;
     if (piece % 16 != 0) return set_error(AC_ERR_INVALID, "ac_serve_create: piece_bytes must be a multiple of 16");
-    if (slots > 64) return set_error(AC_ERR_INVALID, "ac_serve_create: at most 64 slots");
+    if (slots > kMaxSlots) return set_error(AC_ERR_INVALID, "ac_serve_create: at most 64 slots");
+    if (n_autos > kMaxAutos) return set_error(AC_ERR_INVALID, "ac_serve_create: at most 256 automata");
+    if (opts && (opts->flags & ~uint32_t(AC_SERVE_MERGED)))
+        return set_error(AC_ERR_INVALID, "ac_serve_create: unknown flags");
 
     ac_server *s = new (std::nothrow) ac_server();
     if (!s) return set_error(AC_ERR_NOMEM, "ac_serve_create: out of host memory");
@@ -491,6 +857,7 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     s->rate.assign(n_autos, rate);
     s->rate0 = rate;
     s->piece = piece;
+    s->merge = opts && (opts->flags & AC_SERVE_MERGED);
     s->t0 = Clock::now();
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s->pool_base), budget);
     if (e != hipSuccess) {
@@ -514,6 +881,22 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
         for (uint32_t k = 0; k < kPieceEvents && e == hipSuccess; ++k)
             e = hipEventCreateWithFlags(&sl.piece[k], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->d_autos), kMaxAutos * sizeof(acm::dfa::DfaArgs));
+    for (uint32_t i = 0; i < n_autos && e == hipSuccess; ++i) e = upload_auto(s, i);
+    s->launches.resize(kLaunches);
+    for (MergedLaunch &L : s->launches) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&L.h_tasks), kMaxTasks * sizeof(acm::dfa::ServedTask), 0);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&L.d_tasks), kMaxTasks * sizeof(acm::dfa::ServedTask));
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&L.h_demux), kMaxSlots * sizeof(DemuxSlot), 0);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&L.d_demux), kMaxSlots * sizeof(DemuxSlot));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&L.d_count), 16);  // count, then task counter
+        if (e == hipSuccess) L.d_next = reinterpret_cast<uint32_t *>(L.d_count + 1);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&L.h_count), sizeof(uint64_t), 0);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&L.h_words), size_t(slots) * 16, 0);
+    }
     if (e != hipSuccess) {
         destroy(s);
         return set_error(AC_ERR_HIP, std::string("ac_serve_create: ") + hipGetErrorString(e));
@@ -533,9 +916,16 @@ int ac_serve_add(ac_server *s, const ac_automaton *a, uint32_t *id) {
     if (!a->on_device || a->device != s->device || a->m.goto_only)
         return set_error(AC_ERR_INVALID, "ac_serve_add: automaton is host-only, goto-only or on another device");
     std::lock_guard<std::mutex> g(s->mu);
+    if (s->autos.size() >= kMaxAutos) return set_error(AC_ERR_INVALID, "ac_serve_add: at most 256 automata");
     *id = uint32_t(s->autos.size());
     s->autos.push_back(a);
     s->rate.push_back(s->rate0);
+    const hipError_t e = upload_auto(s, *id);
+    if (e != hipSuccess) {
+        s->autos.pop_back();
+        s->rate.pop_back();
+        return set_error(AC_ERR_HIP, std::string("ac_serve_add: ") + hipGetErrorString(e));
+    }
     return AC_OK;
 }
 
@@ -628,6 +1018,7 @@ int ac_serve_stats(ac_server *s, ac_serve_stats_t *st) {
     st->pool_used = s->pool.used();
     st->pool_peak = s->pool.peak();
     st->running_peak = s->running_peak;
+    st->merged_launches = s->merged_launches;
     st->bytes_done = s->bytes_done;
     st->p50_ms = st->p99_ms = st->gbps = 0.0;
     if (!s->latency.empty()) {

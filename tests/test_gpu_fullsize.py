@@ -110,7 +110,7 @@ def test_full_served_configuration():
     sample = set(sample_indices(w.length, 16, 1 << 20))
     served_keys = {}
     for i, t in enumerate(tickets):
-        r = srv.wait(t)
+        r = srv.wait(t, 60_000)  # fails the test instead of hanging it
         assert r.n_matches == plain_counts[i], i
         if i in sample:
             served_keys[i] = np.sort(srv.keys(r))

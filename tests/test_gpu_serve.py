@@ -81,28 +81,40 @@ def submit_all(srv, reqs, together=True):
     return keep, tickets
 
 
+WAIT_MS = 60_000  # a request not done by then fails the test instead of hanging it
+
+
 def collect(srv, tickets):
     out = []
     for t in tickets:
-        r = srv.wait(t)
+        r = srv.wait(t, WAIT_MS)
         assert r.status == 0
         out.append((np.sort(srv.keys(r)), r.pieces, r.rescans, r))
         srv.release(t)
     return out
 
 
-def test_mix_equals_alone_and_oracle(setup):
+MODES = [0, ac.AC_SERVE_MERGED]  # one stream per request (default), shared launches
+
+
+@pytest.mark.parametrize("flags", MODES)
+def test_mix_equals_alone_and_oracle(setup, flags):
     sets, autos, reqs, expect = setup
-    srv = ac.Server(autos, hbm_budget=64 << 20, max_inflight=8, piece_bytes=PIECE)
+    srv = ac.Server(autos, hbm_budget=64 << 20, max_inflight=8, piece_bytes=PIECE, flags=flags)
     keep, tickets = submit_all(srv, reqs)
     mix = collect(srv, tickets)
     st = srv.stats()
     note("mix stats", st)
     assert st["completed"] == len(reqs) and st["failed"] == 0 and st["queued"] == 0
     assert st["running_peak"] > 1  # requests overlapped on the device
+    if flags & ac.AC_SERVE_MERGED:
+        assert 0 < st["merged_launches"] < len(reqs)  # requests shared launches
+    else:
+        assert st["merged_launches"] == 0
     for i, ((keys, pieces, _, r), e) in enumerate(zip(mix, expect)):
         assert np.array_equal(keys, e), i
-        assert pieces == (reqs[i][1].size + PIECE - 1) // PIECE
+        per_request = (reqs[i][1].size + PIECE - 1) // PIECE
+        assert pieces == per_request or (flags and pieces == 1), (i, pieces)
         assert r.t_submit_ns <= r.t_admit_ns <= r.t_done_ns
     # each request alone, on the same server
     for i, (a, text, on_dev) in enumerate(reqs):
@@ -126,12 +138,13 @@ def test_mix_equals_plain_scans(setup):
     srv.close()
 
 
-def test_small_budget_admits_by_memory(setup):
+@pytest.mark.parametrize("flags", MODES)
+def test_small_budget_admits_by_memory(setup, flags):
     """A budget that holds only a few requests at a time: admission waits for
     memory, every result is still exact, and the pool never exceeds it."""
     sets, autos, reqs, expect = setup
     budget = 1 << 20
-    srv = ac.Server(autos, hbm_budget=budget, max_inflight=16, piece_bytes=PIECE)
+    srv = ac.Server(autos, hbm_budget=budget, max_inflight=16, piece_bytes=PIECE, flags=flags)
     host_reqs = [(a, t, False) for a, t, _ in reqs]  # host texts take pool memory too
     keep, tickets = submit_all(srv, host_reqs)
     got = collect(srv, tickets)
@@ -144,14 +157,15 @@ def test_small_budget_admits_by_memory(setup):
     srv.close()
 
 
-def test_low_match_estimate_rescans_exactly(setup):
+@pytest.mark.parametrize("flags", MODES)
+def test_low_match_estimate_rescans_exactly(setup, flags):
     """A match-rate guess far too low: requests overflow their lists and are
     scanned again into exact ones."""
     sets, autos, reqs, expect = setup
     # largest first, so the first requests admitted overflow before any
     # finished request can teach the server a better rate
     order = sorted(range(len(reqs)), key=lambda i: -reqs[i][1].size)
-    srv = ac.Server(autos, piece_bytes=PIECE, match_ppm=1, max_inflight=4)
+    srv = ac.Server(autos, piece_bytes=PIECE, match_ppm=1, max_inflight=4, flags=flags)
     keep, tickets = submit_all(srv, [reqs[i] for i in order])
     got = collect(srv, tickets)
     for g, i in zip(got, order):
@@ -180,7 +194,7 @@ def test_close_with_unreleased_results(setup):
     srv = ac.Server(autos, piece_bytes=PIECE)
     keep, tickets = submit_all(srv, reqs[:10])
     for t in tickets:
-        srv.wait(t)
+        srv.wait(t, WAIT_MS)
     srv.close()  # frees the unreleased lists
 
 
@@ -198,7 +212,7 @@ def test_scheduled_arrivals(setup):
         keep.append(d)
         tickets.append(srv.submit(a, d, n=text.size, on_device=True, arrival_ns=t0 + 1_000_000 * (len(picks) - j)))
     for j, (t, i) in enumerate(zip(tickets, reversed(picks))):
-        r = srv.wait(t)
+        r = srv.wait(t, WAIT_MS)
         assert r.t_submit_ns == t0 + 1_000_000 * (len(picks) - j)
         assert r.t_admit_ns >= r.t_submit_ns and r.t_done_ns >= r.t_admit_ns
         assert np.array_equal(np.sort(srv.keys(r)), expect[i])
@@ -232,12 +246,12 @@ def test_list_larger_than_budget_fails_cleanly():
     big = torch.full((600_000,), ord("A"), dtype=torch.uint8, device="cuda")  # 4.8 MB of keys
     t = srv.submit(0, big, on_device=True)
     with pytest.raises(ac.AcError) as e:
-        srv.wait(t)
+        srv.wait(t, WAIT_MS)
     assert e.value.status == ac.AC_ERR_TOO_LARGE
     srv.release(t)
     small = torch.full((1000,), ord("A"), dtype=torch.uint8, device="cuda")
     t = srv.submit(0, small, on_device=True)
-    r = srv.wait(t)
+    r = srv.wait(t, WAIT_MS)
     assert r.n_matches == 1000
     srv.release(t)
     assert srv.stats()["pool_used"] == 0
@@ -251,5 +265,5 @@ def test_close_while_waiting_for_memory():
     srv = ac.Server([a], hbm_budget=1 << 20, piece_bytes=1 << 16, match_ppm=1_000_000)
     x = torch.full((40_000,), ord("A"), dtype=torch.uint8, device="cuda")  # ~320 KB list each
     tickets = [srv.submit(0, x, on_device=True) for _ in range(6)]
-    srv.wait(tickets[0])  # held, never released
+    srv.wait(tickets[0], WAIT_MS)  # held, never released
     srv.close()
