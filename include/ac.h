@@ -75,7 +75,13 @@ enum {
      * patterns ending at each state, without failure function, output unions
      * or full DFA. Cheaper to build (Sec. IV.A, the cost the paper reduces);
      * such an automaton scans with AC_ALGO_PFAC only. */
-    AC_BUILD_GOTO_ONLY = 1
+    AC_BUILD_GOTO_ONLY = 1,
+    /* Also build two-byte rows for the states outside the LDS_HOT image
+     * (4-column hashed machines with an image and at most 2^20 such states):
+     * a DFA scan then looks up two bytes at once from those states. Halves
+     * the dependent global lookups, but the rows are 16 times the one-byte
+     * rows and miss L2 more often, so it is off by default. */
+    AC_BUILD_PAIR_ROWS = 2
 };
 
 typedef struct {
@@ -92,7 +98,8 @@ typedef struct {
     uint64_t out_entries;  /* total entries of all output sets */
     double build_ms;       /* host time spent constructing the machine */
     uint32_t goto_only;    /* 1 if built with AC_BUILD_GOTO_ONLY */
-    uint32_t reserved;
+    uint32_t pair_states;  /* states outside the LDS_HOT image with two-byte rows
+                              (built with AC_BUILD_PAIR_ROWS); 0 if none */
 } ac_info_t;
 
 /*
@@ -135,7 +142,10 @@ enum {
     AC_TABLE_HOT_DFA = 6, /* uint16 [hot_states][n_cols] (plus one zero if the count is
                              odd): DFA rows of the LDS image, successor | 1<<15 if final */
     AC_TABLE_HOT_GO = 7,  /* uint16 [hot_states][n_cols]: goto rows of the LDS image */
-    AC_TABLE_CMAP = 8     /* uint8 [256]: byte -> column, 255 = byte in no pattern */
+    AC_TABLE_CMAP = 8,    /* uint8 [256]: byte -> column, 255 = byte in no pattern */
+    AC_TABLE_PAIR = 9     /* uint32 [pair_states][16]: row s - hot_states, column
+                             c1 | c2 << 2 = state after classes c1, c2 from s,
+                             | 1<<31 if the state after c1 is final (empty if none) */
 };
 
 /*
@@ -165,7 +175,13 @@ typedef struct {
                            0 = auto */
     uint32_t block_bytes; /* DFA: text bytes a walker loads at once (64 or 128);
                              0 = auto */
+    uint32_t pair_steps;  /* DFA, LDS_HOT: AC_PAIR_AUTO = a walker outside the image
+                             looks up two bytes at once when the automaton was
+                             built with AC_BUILD_PAIR_ROWS (ac_info_t.pair_states
+                             > 0); AC_PAIR_OFF = one byte per lookup */
 } ac_scan_opts;
+
+enum { AC_PAIR_AUTO = 0, AC_PAIR_OFF = 1 };
 
 /*
  * ac_scan -- process the text with the machine in one pass (Sec. II, step 2)

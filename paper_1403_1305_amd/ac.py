@@ -34,10 +34,12 @@ AC_ALGO_DFA = 0
 AC_ALGO_PFAC = 1
 
 AC_BUILD_GOTO_ONLY = 1
+AC_BUILD_PAIR_ROWS = 2
 AC_SERVE_MERGED = 2
+AC_PAIR_AUTO, AC_PAIR_OFF = 0, 1
 
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
-    AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP = range(9)
+    AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP, AC_TABLE_PAIR = range(10)
 
 _TABLE_DTYPE = {AC_TABLE_HOT_DFA: np.uint16, AC_TABLE_HOT_GO: np.uint16, AC_TABLE_CMAP: np.uint8}
 
@@ -62,13 +64,14 @@ class ac_info_t(ctypes.Structure):
                 ("hot_states", ctypes.c_uint32), ("class_shift", ctypes.c_uint32),
                 ("class_hashed", ctypes.c_uint32), ("table_bytes", ctypes.c_uint64),
                 ("out_entries", ctypes.c_uint64), ("build_ms", ctypes.c_double),
-                ("goto_only", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("goto_only", ctypes.c_uint32), ("pair_states", ctypes.c_uint32)]
 
 
 class ac_scan_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("block", ctypes.c_uint32), ("placement", ctypes.c_uint32),
-                ("walkers", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32)]
+                ("walkers", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32),
+                ("pair_steps", ctypes.c_uint32)]
 
 
 class ac_batch_tune(ctypes.Structure):
@@ -262,8 +265,8 @@ def ac_get_table(a: Automaton, which: int) -> np.ndarray:
     return out[: size.value // np.dtype(dt).itemsize]
 
 
-def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0, walkers=0, block_bytes=0):
-    return ac_scan_opts(algo, chunk, block, placement, walkers, block_bytes)
+def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0, walkers=0, block_bytes=0, pair_steps=0):
+    return ac_scan_opts(algo, chunk, block, placement, walkers, block_bytes, pair_steps)
 
 
 def ac_scan(a: Automaton, d_text, n: int, d_matches, capacity: int, d_count,

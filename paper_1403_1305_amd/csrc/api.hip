@@ -46,6 +46,32 @@ int upload(ac_automaton *a, const std::vector<T> &v, const T **dst, hipStream_t 
     return AC_OK;
 }
 
+// The DFA table, followed (from a word offset that is a multiple of 16) by
+// the two-byte rows when the machine has them, in one device allocation.
+int upload_dfa(ac_automaton *a, const acm::Machine &m, acm::DeviceMachine &dm, hipStream_t stream) {
+    dm.dfa = nullptr;
+    dm.pair_states = 0;
+    dm.pair_base = 0;
+    if (m.dfa.empty()) return AC_OK;
+    const size_t base = m.pair.empty() ? m.dfa.size() : (m.dfa.size() + 15) & ~size_t(15);
+    const size_t words = base + m.pair.size();
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, words * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(AC_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    a->allocations.push_back(p);
+    uint32_t *d = static_cast<uint32_t *>(p);
+    e = hipMemcpyAsync(d, m.dfa.data(), m.dfa.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !m.pair.empty())
+        e = hipMemcpyAsync(d + base, m.pair.data(), m.pair.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(AC_ERR_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    dm.dfa = d;
+    if (!m.pair.empty()) {
+        dm.pair_states = m.pair_states;
+        dm.pair_base = uint32_t(base);
+    }
+    return AC_OK;
+}
+
 void release(ac_automaton *a) {
     for (void *p : a->allocations) (void)hipFree(p);
     a->allocations.clear();
@@ -58,7 +84,7 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
     const uint32_t place = opts ? opts->placement : AC_PLACE_AUTO;
     if (place > AC_PLACE_LDS_HOT) return fail(AC_ERR_INVALID, "ac_build: unknown placement");
     const uint32_t flags = opts ? opts->flags : 0u;
-    if (flags & ~uint32_t(AC_BUILD_GOTO_ONLY)) return fail(AC_ERR_INVALID, "ac_build: unknown flags");
+    if (flags & ~uint32_t(AC_BUILD_GOTO_ONLY | AC_BUILD_PAIR_ROWS)) return fail(AC_ERR_INVALID, "ac_build: unknown flags");
     a = new (std::nothrow) ac_automaton();
     if (!a) return fail(AC_ERR_NOMEM, "ac_build: out of host memory");
     const uint32_t budget = lds_budget(opts);
@@ -69,6 +95,7 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
         plan.only_if_needed = place == AC_PLACE_AUTO;
     }
     plan.goto_only = (flags & AC_BUILD_GOTO_ONLY) != 0;
+    plan.pair_rows = (flags & AC_BUILD_PAIR_ROWS) != 0;
     plan.threads = opts ? opts->threads : 0u;
     std::string err;
     int rc;
@@ -145,7 +172,7 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
     dm.hash_shift = m.hash_shift;
     std::memcpy(dm.hash_letter, m.hash_letter, sizeof(dm.hash_letter));
     std::vector<uint8_t> cmap(m.cmap, m.cmap + 256);
-    if ((rc = upload(a, m.dfa, &dm.dfa, s)) || (rc = upload(a, m.go, &dm.go, s)) ||
+    if ((rc = upload_dfa(a, m, dm, s)) || (rc = upload(a, m.go, &dm.go, s)) ||
         (rc = upload(a, m.out_off, &dm.out_off, s)) || (rc = upload(a, m.out_ids, &dm.out_ids, s)) ||
         (rc = upload(a, m.own_off, &dm.own_off, s)) || (rc = upload(a, m.own_ids, &dm.own_ids, s)) ||
         (rc = upload(a, m.hot_dfa, &dm.hot_dfa, s)) || (rc = upload(a, m.hot_go, &dm.hot_go, s)) ||
@@ -196,7 +223,7 @@ int ac_info(const ac_automaton *a, ac_info_t *info) {
     info->class_hashed = a->m.hashed ? 1u : 0u;
     info->table_bytes = a->m.goto_only ? 0ull : uint64_t(a->m.n_states) * a->m.n_cols * 4ull;
     info->goto_only = a->m.goto_only ? 1u : 0u;
-    info->reserved = 0;
+    info->pair_states = a->m.pair_states;
     info->out_entries = a->m.out_ids.size();
     info->build_ms = a->m.build_ms;
     return AC_OK;
@@ -218,6 +245,7 @@ int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_
         case AC_TABLE_HOT_DFA: src = m.hot_dfa.data(); sz = m.hot_dfa.size() * 2; break;
         case AC_TABLE_HOT_GO: src = m.hot_go.data(); sz = m.hot_go.size() * 2; break;
         case AC_TABLE_CMAP: src = m.cmap; sz = 256; break;
+        case AC_TABLE_PAIR: src = m.pair.data(); sz = m.pair.size() * 4; break;
         default: return fail(AC_ERR_INVALID, "ac_get_table: unknown table");
     }
     *bytes = sz;
@@ -244,7 +272,9 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         cfg.block = opts->block;
         cfg.walkers = opts->walkers;
         cfg.block_bytes = opts->block_bytes;
+        cfg.pair_steps = opts->pair_steps == AC_PAIR_AUTO;
         want = opts->placement;
+        if (opts->pair_steps > AC_PAIR_OFF) return fail(AC_ERR_INVALID, "ac_scan: unknown pair_steps");
     }
     if (cfg.algo > AC_ALGO_PFAC) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
     if (cfg.algo == AC_ALGO_DFA && a->m.goto_only)
@@ -288,7 +318,9 @@ int ac_scan_stream(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uin
         cfg.block = opts->block;
         cfg.walkers = opts->walkers;
         cfg.block_bytes = opts->block_bytes;
+        cfg.pair_steps = opts->pair_steps == AC_PAIR_AUTO;
         want = opts->placement;
+        if (opts->pair_steps > AC_PAIR_OFF) return fail(AC_ERR_INVALID, "ac_scan_stream: unknown pair_steps");
     }
     if (!resolve_placement(a, want, cfg.placement))
         return fail(AC_ERR_INVALID, "ac_scan_stream: placement not available for this automaton");

@@ -61,9 +61,12 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
         err = "ac_scan: this placement runs with " + std::to_string(block) + " threads per workgroup";
         return AC_ERR_INVALID;
     }
+    // two-byte lookups from the states outside the image, where built
+    const bool pair = cfg.placement == AC_PLACE_LDS_HOT && cfg.pair_steps && dm.pair_states > 0;
     // text block: whole cache lines (128 B, one buffer: a line is fetched
-    // once) unless four walkers need the registers (64 B, one buffer)
-    const uint32_t bb = cfg.block_bytes ? cfg.block_bytes : (K >= 3 ? 64u : 128u);
+    // once) unless three or four walkers need the registers (64 B, one
+    // buffer); the two-byte walk runs best on 64 B blocks in two buffers
+    const uint32_t bb = cfg.block_bytes ? cfg.block_bytes : (K >= 3 || pair ? 64u : 128u);
     if (bb != 64 && bb != 128) {
         err = "ac_scan: block_bytes must be 64 or 128";
         return AC_ERR_INVALID;
@@ -72,7 +75,10 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
     switch (cfg.placement) {
         case AC_PLACE_GLOBAL: kernel = dfa::select_global(dm, K, bb); break;
         case AC_PLACE_LDS_FULL: kernel = dfa::select_full(dm, K, bb); break;
-        case AC_PLACE_LDS_HOT: kernel = dfa::select_hot(dm, K, bb); break;
+        case AC_PLACE_LDS_HOT:
+            kernel = pair ? dfa::select_hot_pair(dm, K, bb) : nullptr;
+            if (!kernel) kernel = dfa::select_hot(dm, K, bb);
+            break;
     }
     if (!kernel) {
         err = "ac_scan: no kernel for this placement / walker count";

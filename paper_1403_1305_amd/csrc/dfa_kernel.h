@@ -47,6 +47,7 @@ struct DfaArgs {
     uint32_t acc_end;      // final states are exactly [H, acc_end) when H > 0
     uint32_t table_words;  // LDS_FULL: n_states * n_cols
     uint32_t hash_shift;   // hashed classes: column = (b >> shift) & (n_cols - 1)
+    uint32_t pair_base;    // word of dfa where the two-byte rows of states >= hot start
     uint32_t letters_lo, letters_hi;  // the letter owning each hashed column
     const uint32_t *dfa;
     const uint16_t *hot_rows;
@@ -76,6 +77,11 @@ __device__ __forceinline__ uint32_t lookup(uint32_t s, uint32_t c, const DfaArgs
     } else {
         return a.dfa[idx];
     }
+}
+
+// 16-bit image entry at a byte offset into the image.
+__device__ __forceinline__ uint32_t lds_u16(const uint16_t *image, uint32_t byte_off) {
+    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(image) + byte_off);
 }
 
 // One byte with the general byte map: bytes in no pattern reset to the root.
@@ -131,8 +137,10 @@ __device__ __forceinline__ void load_block(TextBlock<G> &b, const uint8_t *text,
     }
 }
 
-// The walkers of one lane, stepping K chunks in lockstep.
-template <int PLACE, int K, int LOG2C, bool HASHED>
+// The walkers of one lane, stepping K chunks in lockstep. With PAIR (LDS_HOT,
+// four hashed columns, two-byte rows built) a walker outside the image looks
+// up two bytes at once.
+template <int PLACE, int K, int LOG2C, bool HASHED, bool PAIR = false>
 struct Walkers {
     const DfaArgs &a;
     const uint8_t *s_cmap;
@@ -184,6 +192,60 @@ struct Walkers {
                     }
                 }
             }
+        } else if constexpr (HASHED && PAIR) {
+            static_assert(PLACE == AC_PLACE_LDS_HOT && LOG2C == 2, "two-byte rows exist for the 4-column image only");
+            // Two bytes per step. A walker in an image state takes the first
+            // byte from the image; a walker outside it reads its two-byte row
+            // in global memory, and one that leaves the image on the first byte
+            // reads the second byte's row there: at most one global load per
+            // walker per two bytes, so half the waits on global memory.
+#pragma unroll
+            for (int j = 0; j < 16; j += 2) {
+                const uint32_t sh = (j & 3) * 8;
+                uint32_t c1[K], c2[K], e1[K], e2[K], g[K];
+                bool cs[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t hw = j < 4 ? h[k].x : j < 8 ? h[k].y : j < 12 ? h[k].z : h[k].w;
+                    c1[k] = (hw >> sh) & 3u;
+                    c2[k] = (hw >> (sh + 8)) & 3u;
+                    cs[k] = s[k] >= a.hot;
+                    e1[k] = lds_u16(s_hot, (min(s[k], a.hot - 1u) << 3) | (c1[k] << 1));
+                }
+                bool need = false;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    // second byte from the image, read before any global wait
+                    e2[k] = lds_u16(s_hot, (min(e1[k], a.hot - 1u) << 3) | (c2[k] << 1));
+                    need |= cs[k] || e1[k] >= a.hot;
+                    g[k] = 0;
+                }
+                if (__any(need)) {
+                    // image walkers read entry 0, one shared line
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const bool ce = !cs[k] && e1[k] >= a.hot;
+                        const uint32_t idx = cs[k] ? (s[k] << 4) + (a.pair_base - (a.hot << 4)) + (c1[k] | (c2[k] << 2))
+                                                   : ce ? ((e1[k] << 2) | c2[k]) : 0u;
+                        g[k] = a.dfa[idx];
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        // final states: the one a walker outside the image stands
+                        // in (entered at byte j-1) and the one after byte j
+                        if (cs[k] && j > 0 && s[k] < a.acc_end) flag[k] |= kAccept;
+                        if (cs[k])
+                            flag[k] |= g[k] & kAccept;
+                        else if (e1[k] - a.hot < a.acc_end - a.hot)
+                            flag[k] |= kAccept;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) s[k] = (cs[k] || e1[k] >= a.hot) ? (g[k] & kStateMask) : e2[k];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (s[k] - a.hot < a.acc_end - a.hot) flag[k] |= kAccept;
         } else if constexpr (HASHED) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
@@ -340,8 +402,8 @@ __device__ __forceinline__ void load_tables(const DfaArgs &a, uint8_t *s_cmap, u
 // (wstart a multiple of 16) from state s[k]; a walker without a chunk has
 // own = hi = wstart = 0 and walks nothing. On return s[k] is the state after
 // byte hi[k] - 1.
-template <int PLACE, int K, int LOG2C, bool HASHED, int NBUF, int G>
-__device__ __forceinline__ void walk_chunks(const Walkers<PLACE, K, LOG2C, HASHED> &W, const DfaArgs &a,
+template <int PLACE, int K, int LOG2C, bool HASHED, int NBUF, int G, bool PAIR = false>
+__device__ __forceinline__ void walk_chunks(const Walkers<PLACE, K, LOG2C, HASHED, PAIR> &W, const DfaArgs &a,
                                             Emitter &em, const uint8_t *s_cmap, const uint32_t *s_tab,
                                             const uint16_t *s_hot, uint32_t (&s_io)[K],
                                             const uint32_t (&own_in)[K], const uint32_t (&hi_in)[K],
@@ -396,7 +458,7 @@ __device__ __forceinline__ void walk_chunks(const Walkers<PLACE, K, LOG2C, HASHE
     for (int k = 0; k < K; ++k) s_io[k] = s[k];
 }
 
-template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
+template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G, bool PAIR = false>
 __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
     // LDS: per-wave match queues | byte map (256 B) | table image
     extern __shared__ __align__(16) uint8_t smem[];
@@ -409,7 +471,7 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
     em.init(smem, a.out, a.cap, a.count);
     load_tables<PLACE, BLOCK>(a, s_cmap, s_tab, s_hot);
 
-    const Walkers<PLACE, K, LOG2C, HASHED> W{a, s_cmap, s_tab, s_hot, em};
+    const Walkers<PLACE, K, LOG2C, HASHED, PAIR> W{a, s_cmap, s_tab, s_hot, em};
     const uint32_t lanes = gridDim.x * BLOCK;
     const uint32_t lane = blockIdx.x * BLOCK + tid;
 
@@ -429,7 +491,7 @@ __global__ void __launch_bounds__(BLOCK) dfa_kernel(DfaArgs a) {
             // state the text's earlier pieces ended in (the root for a new text)
             s[k] = (act && own[k] <= a.back && a.state_in) ? *a.state_in : 0u;
         }
-        walk_chunks<PLACE, K, LOG2C, HASHED, NBUF, G>(W, a, em, s_cmap, s_tab, s_hot, s, own, hi, wstart);
+        walk_chunks<PLACE, K, LOG2C, HASHED, NBUF, G, PAIR>(W, a, em, s_cmap, s_tab, s_hot, s, own, hi, wstart);
         // the last chunk's walker ends exactly in the text's final state: it
         // walked at least m_max bytes or started from the carried state
 #pragma unroll
@@ -608,6 +670,7 @@ inline void fill_machine_args(const DeviceMachine &dm, DfaArgs &a) {
     a.acc_end = dm.acc_end;
     a.table_words = dm.n_states * dm.n_cols;
     a.hash_shift = dm.hash_shift;
+    a.pair_base = dm.pair_base;
     a.letters_lo = uint32_t(dm.hash_letter[0]) | uint32_t(dm.hash_letter[1]) << 8 |
                    uint32_t(dm.hash_letter[2]) << 16 | uint32_t(dm.hash_letter[3]) << 24;
     a.letters_hi = uint32_t(dm.hash_letter[4]) | uint32_t(dm.hash_letter[5]) << 8 |
@@ -709,6 +772,8 @@ ServedKernel select_served_global(bool hashed, int l2, uint32_t K, uint32_t bloc
 DfaKernel select_global(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 DfaKernel select_full(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 DfaKernel select_hot(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
+// LDS_HOT with two-byte rows (four hashed columns); nullptr for other machines.
+DfaKernel select_hot_pair(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 
 }  // namespace dfa
 }  // namespace acm

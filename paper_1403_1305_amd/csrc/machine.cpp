@@ -415,6 +415,25 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
             if (full) m.hot_dfa[size_t(f) * C + c] = uint16_t(m.dfa[size_t(f) * C + c] & kStateMask);
             m.hot_go[size_t(f) * C + c] = uint16_t(m.go[size_t(f) * C + c] & kStateMask);
         }
+    // Two bytes per lookup from the states outside the image (on request):
+    // half as many dependent global lookups for the walks that leave it.
+    m.pair.clear();
+    m.pair_states = 0;
+    if (plan.pair_rows && full && m.hashed && C == 4 && H > 0 && S - H <= kPairMaxStates) {
+        m.pair_states = S - H;
+        m.pair.assign(size_t(S - H) * 16, 0);
+        parallel_for(NT, S - H, [&](size_t b0, size_t e0) {
+            for (size_t i = b0; i < e0; ++i) {
+                const size_t s = H + i;
+                for (uint32_t c1 = 0; c1 < 4; ++c1) {
+                    const uint32_t mid = m.dfa[s * 4 + c1];
+                    const size_t row = size_t(mid & kStateMask) * 4;
+                    for (uint32_t c2 = 0; c2 < 4; ++c2)
+                        m.pair[i * 16 + (c1 | c2 << 2)] = (m.dfa[row + c2] & kStateMask) | (mid & kAccept);
+                }
+            }
+        });
+    }
     // 16-bit images are copied as 32-bit words: pad them to whole words
     if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);
     if (m.hot_go.size() & 1) m.hot_go.push_back(0);

@@ -25,6 +25,9 @@ constexpr uint32_t kHotIdLimit = 1u << 16;
 constexpr uint32_t kMinHotStates = 256;
 // byte -> column map value for bytes that occur in no pattern
 constexpr uint8_t kNoClass = 0xffu;
+// Two-byte rows are built for at most this many states outside the image
+// (16 four-byte entries each: 64 MiB at the limit).
+constexpr uint32_t kPairMaxStates = 1u << 20;
 
 struct Machine {
     uint32_t n_patterns = 0;
@@ -61,6 +64,12 @@ struct Machine {
     uint32_t hot_states = 0;
     std::vector<uint16_t> hot_dfa;  // hot_states * n_cols successor ids
     std::vector<uint16_t> hot_go;   // hot_states * n_cols goto children, 0 = no edge
+    // Two-byte rows of the states outside the image, for 4-column hashed
+    // machines with an image: pair[(s - H) * 16 + (c1 | c2 << 2)] is the state
+    // after bytes of classes c1 then c2 from s, | kAccept if the state after
+    // c1 is final. Empty when not built (pair_states == 0).
+    std::vector<uint32_t> pair;
+    uint32_t pair_states = 0;
     double build_ms = 0.0;
 };
 
@@ -74,6 +83,7 @@ struct HotPlan {
     // of Sec. II.B, all that the per-start-position matcher needs).
     bool goto_only = false;
     uint32_t threads = 0;        // host threads for the build, 0 = hardware threads (at most 16)
+    bool pair_rows = false;      // also build Machine::pair where it applies
 };
 
 // Returns 0 or a negative AC_ERR_* code with `err` set. Without an image,

@@ -21,6 +21,9 @@ struct DeviceMachine {
     const uint32_t *own_off = nullptr, *own_ids = nullptr;
     const uint16_t *hot_dfa = nullptr, *hot_go = nullptr;
     const uint8_t *cmap = nullptr;  // 256 bytes
+    // Two-byte rows (Machine::pair) live in the dfa allocation from word
+    // pair_base on (a multiple of 16); pair_states == 0 when there are none.
+    uint32_t pair_states = 0, pair_base = 0;
 };
 
 struct ScanConfig {
@@ -30,6 +33,7 @@ struct ScanConfig {
     uint32_t walkers = 0;    // DFA chunks walked per lane (1 to 4), 0 = auto
     uint32_t block_bytes = 0;  // DFA text bytes per walker load (64, 128), 0 = auto
     uint32_t placement = 0;  // resolved AC_PLACE_* (never AUTO here)
+    bool pair_steps = true;  // LDS_HOT: two-byte lookups from cold states when built
 };
 
 // LDS bytes a workgroup may use on gfx950.

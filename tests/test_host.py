@@ -206,6 +206,37 @@ def test_hot_image_for_large_dna_set():
     assert np.array_equal(t.dfa_walk(text), oracle.oracle_match(text, w.patterns))
 
 
+def test_pair_rows_compose_two_steps():
+    """The two-byte rows (built on request) of the states outside the image
+    are the DFA applied twice, flagged where the state in between has a
+    non-empty output set; machines without four hashed columns or without an
+    image get none."""
+    w = plain_workload("dna256m", n=1 << 16)
+    pats = w.patterns[:3000]
+    assert ac.ac_info(build_host(pats, placement=ac.AC_PLACE_LDS_HOT))["pair_states"] == 0  # not asked for
+    a = build_host(pats, placement=ac.AC_PLACE_LDS_HOT, lds_bytes=2048 * 8 + 256, flags=ac.AC_BUILD_PAIR_ROWS)
+    info = ac.ac_info(a)
+    S, H, C = info["n_states"], info["hot_states"], info["n_cols"]
+    assert C == 4 and H == 2048 and info["pair_states"] == S - H
+    dfa = ac.ac_get_table(a, ac.AC_TABLE_DFA).reshape(S, C).astype(np.int64)
+    pair = ac.ac_get_table(a, ac.AC_TABLE_PAIR).reshape(S - H, 16).astype(np.int64)
+    final = np.diff(ac.ac_get_table(a, ac.AC_TABLE_OUT_OFF).astype(np.int64)) > 0
+    mask = (1 << 31) - 1
+    cold = np.arange(H, S)
+    for c1 in range(4):
+        mid = dfa[cold, c1] & mask
+        for c2 in range(4):
+            got = pair[:, c1 | c2 << 2]
+            assert np.array_equal(got & mask, dfa[mid, c2] & mask)
+            assert np.array_equal((got >> 31) & 1, final[mid].astype(np.int64))
+    # a final state in between does occur among the rows checked
+    assert any(final[dfa[cold, c] & mask].any() for c in range(4))
+    flag = ac.AC_BUILD_PAIR_ROWS
+    assert ac.ac_info(build_host([b"ACGT", b"GATTACA"], flags=flag))["pair_states"] == 0  # whole table in LDS
+    prot = plain_workload("protein1g", n=1 << 12).patterns[:500]
+    assert ac.ac_info(build_host(prot, placement=ac.AC_PLACE_LDS_HOT, flags=flag))["pair_states"] == 0
+
+
 def test_large_protein_set_builds():
     """50,000 protein patterns: more final states than 16-bit ids can hold
     beside an image, so the build must fall back cleanly (no image)."""
@@ -257,7 +288,7 @@ def test_goto_only_build_walks_like_the_oracle(c):
 
 def test_goto_only_rejects_dfa_uses():
     with pytest.raises(ac.AcError):
-        build_host([b"AB"], flags=2)  # unknown flag
+        build_host([b"AB"], flags=4)  # unknown flag
 
 
 @pytest.mark.parametrize("flags", [0, ac.AC_BUILD_GOTO_ONLY])
