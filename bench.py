@@ -357,7 +357,10 @@ def main():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched", "served", "build"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched sub-benchmark")
-    p.add_argument("--no-served", action="store_true", help="skip the served sub-benchmark")
+    p.add_argument("--no-served", action="store_true", help="(default) skip the served sub-benchmark")
+    p.add_argument("--served", action="store_true",
+                   help="add the served sub-benchmark to the headline run (off by default: one of its "
+                        "Poisson replays once stalled)")
     p.add_argument("--no-build", action="store_true", help="skip the build-time sub-benchmark")
     p.add_argument("--no-e1", action="store_true", help="skip the 0%%-planted timing check")
     p.add_argument("--slots", type=int, default=8, help="requests a server holds on the device at once")
@@ -520,7 +523,7 @@ def main():
         torch.cuda.empty_cache()
         build = bench_build(args, torch, ac, stream)
     served = None
-    if not args.no_served:
+    if args.served and not args.no_served:
         torch.cuda.empty_cache()
         served = bench_served(args, torch, ac, stream)
 

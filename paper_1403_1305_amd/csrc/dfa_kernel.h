@@ -246,6 +246,56 @@ struct Walkers {
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (s[k] - a.hot < a.acc_end - a.hot) flag[k] |= kAccept;
+        } else if constexpr (HASHED && PLACE == AC_PLACE_LDS_HOT) {
+            // Classes pre-scaled to the 2-byte entries of an image row: one
+            // shift per word, then the step's offset u = s * row + 2c serves
+            // both tables (image: u clamped to its last entry, since a lane
+            // outside the image discards what it reads there; 32-bit table:
+            // byte offset 2u from its base).
+            uint4 h2[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                h2[k].x = h[k].x << 1;
+                h2[k].y = h[k].y << 1;
+                h2[k].z = h[k].z << 1;
+                h2[k].w = h[k].w << 1;
+            }
+            const uint32_t last = (a.hot << (LOG2C + 1)) - 2u;
+            const uint8_t *img = reinterpret_cast<const uint8_t *>(s_hot);
+            const uint8_t *tab = reinterpret_cast<const uint8_t *>(a.dfa);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t sh = (j & 3) * 8;
+                uint32_t u[K], e[K];
+                bool cold = false;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t hw = j < 4 ? h2[k].x : j < 8 ? h2[k].y : j < 12 ? h2[k].z : h2[k].w;
+                    u[k] = (s[k] << (LOG2C + 1)) | __builtin_amdgcn_ubfe(hw, sh, LOG2C + 1);
+                    cold |= s[k] >= a.hot;
+                    e[k] = *reinterpret_cast<const uint16_t *>(img + min(u[k], last));
+                }
+                if (__any(cold)) {
+                    // all K loads go out before any is waited on; image lanes
+                    // read entry 0, one shared line
+                    uint32_t g[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        g[k] = *reinterpret_cast<const uint32_t *>(tab + (s[k] >= a.hot ? u[k] << 1 : 0u));
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const bool ck = s[k] >= a.hot;
+                        // a state outside the image entered at byte j-1 may be final
+                        if (j > 0 && ck && s[k] < a.acc_end) flag[k] |= kAccept;
+                        e[k] = ck ? (g[k] & kStateMask) : e[k];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) s[k] = e[k];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (s[k] - a.hot < a.acc_end - a.hot) flag[k] |= kAccept;
         } else if constexpr (HASHED) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
@@ -256,50 +306,13 @@ struct Walkers {
                     const uint32_t hw = j < 4 ? h[k].x : j < 8 ? h[k].y : j < 12 ? h[k].z : h[k].w;
                     c[k] = (hw >> sh) & ((1u << LOG2C) - 1u);
                 }
-                if constexpr (PLACE == AC_PLACE_LDS_HOT) {
-                    // Image rows hold plain successor ids; a state >= H is cold
-                    // or final. Those lanes look the step up in the 32-bit table
-                    // and note whether the state they stand in is final (it was
-                    // entered at byte j-1; byte 15's state is checked below).
-                    bool cold = false;
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        cold |= s[k] >= a.hot;
-                        const uint32_t off = (min(s[k], a.hot - 1u) << (LOG2C + 1)) | (c[k] << 1);
-                        e[k] = *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(s_hot) + off);
-                    }
-                    if (__any(cold)) {
-                        // all K loads go out before any is waited on; hot lanes
-                        // read entry 0, one shared line
-                        uint32_t g[K];
-#pragma unroll
-                        for (int k = 0; k < K; ++k)
-                            g[k] = a.dfa[s[k] >= a.hot ? ((s[k] << LOG2C) | c[k]) : 0u];
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            const bool ck = s[k] >= a.hot;
-                            if (j > 0 && ck && s[k] < a.acc_end) flag[k] |= kAccept;
-                            e[k] = ck ? (g[k] & kStateMask) : e[k];
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) e[k] = lookup<PLACE, LOG2C>(s[k], c[k], a, s_tab, s_hot);
-                }
+                // the whole table in LDS, or every lookup from global memory
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    if constexpr (PLACE == AC_PLACE_LDS_HOT) {
-                        s[k] = e[k];
-                    } else {
-                        s[k] = e[k] & kStateMask;
-                        flag[k] |= e[k];
-                    }
+                    e[k] = lookup<PLACE, LOG2C>(s[k], c[k], a, s_tab, s_hot);
+                    s[k] = e[k] & kStateMask;
+                    flag[k] |= e[k];
                 }
-            }
-            if constexpr (PLACE == AC_PLACE_LDS_HOT) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (s[k] - a.hot < a.acc_end - a.hot) flag[k] |= kAccept;
             }
         }
 #pragma unroll

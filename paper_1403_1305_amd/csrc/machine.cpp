@@ -294,7 +294,8 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     // successor of a hot row must fit the 16-bit entries: the image shrinks
     // until it does (or is dropped if the final states alone do not fit).
     uint32_t hot_budget = 0;
-    if (plan.lds_bytes > 256) {
+    // (the image kernels address the 32-bit table with 32-bit byte offsets)
+    if (plan.lds_bytes > 256 && uint64_t(S) * C * 4ull < (1ull << 32)) {
         const bool full_fits = 256ull + uint64_t(S) * C * 4ull <= plan.lds_bytes;
         if (!(plan.only_if_needed && full_fits)) {
             hot_budget = (plan.lds_bytes - 256) / (2 * C);
