@@ -259,6 +259,9 @@ struct Walkers {
                 h2[k].y = h[k].y << 1;
                 h2[k].z = h[k].z << 1;
                 h2[k].w = h[k].w << 1;
+                // hide the known-zero bits, so that each class below stays one
+                // bit-field extract instead of a shift and a mask (no code)
+                asm volatile("" : "+v"(h2[k].x), "+v"(h2[k].y), "+v"(h2[k].z), "+v"(h2[k].w));
             }
             const uint32_t last = (a.hot << (LOG2C + 1)) - 2u;
             const uint8_t *img = reinterpret_cast<const uint8_t *>(s_hot);
