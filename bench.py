@@ -84,10 +84,10 @@ def cpu_baseline(w, sample_bytes, min_s=10.0, max_passes=3):
     import oracle
     ac_cpu = oracle.OracleAC(w.patterns)
     sample = w.text[:sample_bytes]
-    passes, dt = 0, 0.0
+    passes, dt, count = 0, 0.0, 0
     while passes < max_passes and (passes == 0 or dt < min_s):
         t0 = time.perf_counter()
-        ac_cpu.scan(sample)
+        count = ac_cpu.scan(sample).size
         dt += time.perf_counter() - t0
         passes += 1
     model = ""
@@ -99,7 +99,43 @@ def cpu_baseline(w, sample_bytes, min_s=10.0, max_passes=3):
     return {"value": round(passes * len(sample) / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "host_threads": os.cpu_count(), "host_cpu": model,
             "sample": f"{passes} pass(es) over the first {len(sample) >> 20} MiB of the same text, full pattern "
-                      f"set, single-threaded failure-link scan ({dt:.1f} s); build not timed"}
+                      f"set, single-threaded failure-link scan ({dt:.1f} s); build not timed"}, (ac_cpu, sample, count)
+
+
+def cpu_all_cores(ac_cpu, sample, count, m_max, min_s=2.0, max_passes=5):
+    """The same oracle on every host thread (at most 16): the sample is cut
+    into one slice per thread, each read from m_max - 1 bytes before its
+    start and keeping the matches that end inside it (the chunk rule of the
+    GPU scan). Its match count must equal the single-threaded pass."""
+    import threading
+    import numpy as np
+    T = max(1, min(os.cpu_count() or 1, 16))
+    n = len(sample)
+    bounds = [n * t // T for t in range(T + 1)]
+    got = [None] * T
+
+    def work(t):
+        lo, hi = bounds[t], bounds[t + 1]
+        start = max(0, lo - (m_max - 1))
+        keys = ac_cpu.scan(sample[start:hi])
+        ends = (keys >> np.uint64(32)).astype(np.int64) + start
+        got[t] = keys[ends >= lo]
+
+    passes, dt = 0, 0.0
+    while passes < max_passes and (passes == 0 or dt < min_s):
+        threads = [threading.Thread(target=work, args=(t,)) for t in range(T)]
+        t0 = time.perf_counter()
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        dt += time.perf_counter() - t0
+        passes += 1
+    total = int(sum(g.size for g in got))
+    return {"value": round(passes * n / dt / 1e9, 6), "unit": "GB/s", "cores": T, "kind": "oracle, text slices",
+            "exact_count": total == count,
+            "sample": f"{passes} pass(es) over the same {n >> 20} MiB, one slice per thread with an m_max - 1 "
+                      f"byte lead-in ({dt:.1f} s)"}
 
 
 BATCHED_DESC = ("4,096 i.i.d. uniform ACGT texts, lengths log-uniform in [1 KiB, 4 MiB]; 16 resident "
@@ -512,7 +548,12 @@ def main():
         dst.copy_(copies[1])
         torch.cuda.synchronize()
 
-    cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_sample_mib << 20)
+    cpu = cpu_all = None
+    if not args.no_cpu:
+        cpu, (ac_cpu, sample, count) = cpu_baseline(w, args.cpu_sample_mib << 20)
+        log("cpu baseline, all cores")
+        cpu_all = cpu_all_cores(ac_cpu, sample, count, max(len(p) for p in w.patterns))
+        del ac_cpu, sample
     del copies, outs
     batched = None
     if not args.no_batched:
@@ -560,6 +601,7 @@ def main():
         "sort_ms": sort_ms,
         "pfac": pfac,
         "cpu_baseline": cpu,
+        "cpu_all_cores": cpu_all,
         "batched": batched,
         "served": served,
         "build": build,
