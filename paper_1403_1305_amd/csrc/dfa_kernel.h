@@ -137,6 +137,20 @@ __device__ __forceinline__ void load_block(TextBlock<G> &b, const uint8_t *text,
     }
 }
 
+// The first block of a walk: groups wholly before the walk's first byte are
+// not read (zeros stand in; those groups are never walked). A chunk's
+// lead-in then requests only the end of the line before it, which the
+// neighbouring walker reads again much later.
+template <int G>
+__device__ __forceinline__ void load_first_block(TextBlock<G> &b, const uint8_t *text, uint32_t p, bool ok,
+                                                 uint32_t from) {
+    if (ok) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(text + p);
+#pragma unroll
+        for (int i = 0; i < G; ++i) b.g[i] = p + 16u * (i + 1) > from ? q[i] : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
 // The walkers of one lane, stepping K chunks in lockstep. With PAIR (LDS_HOT,
 // four hashed columns, two-byte rows built) a walker outside the image looks
 // up two bytes at once.
@@ -442,7 +456,7 @@ __device__ __forceinline__ void walk_chunks(const Walkers<PLACE, K, LOG2C, HASHE
     for (int k = 0; k < K; ++k) {
         bpos[k] = wstart[k] & ~(BB - 1);
         bend[k] = hi[k] & ~(BB - 1);
-        load_block(A[k], a.text, bpos[k], bpos[k] < bend[k]);
+        load_first_block(A[k], a.text, bpos[k], bpos[k] < bend[k], wstart[k]);
         if constexpr (NBUF == 2)
             load_block(B[k], a.text, bpos[k] + BB, bend[k] > BB && bpos[k] < bend[k] - BB);
     }
