@@ -264,9 +264,12 @@ int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     const uint32_t cus = uint32_t(compute_units(dev));
-    constexpr uint32_t block = 256;
+    // 1024 threads: each walk is a chain of dependent lookups, and with the
+    // image filling the LDS one workgroup per CU is all that fits, so its 16
+    // waves are what hides the lookup latency
+    constexpr uint32_t block = 1024;
     if (cfg.block != 0 && cfg.block != block) {
-        err = "ac_scan: PFAC runs with 256 threads per workgroup";
+        err = "ac_scan: PFAC runs with 1024 threads per workgroup";
         return AC_ERR_INVALID;
     }
     PfacArgs a{};
