@@ -2,22 +2,26 @@
 // instantiated per table placement in dfa_place_*.hip, launched from dfa.hip).
 //
 // The text is cut into chunks of C bytes. Chunk k owns the end positions
-// [kC, min(kC + C, n)); its walker starts from the root exactly m_max - 1
-// bytes before kC (or at 0) and reports only the matches that end inside the
-// chunk. Every occurrence ending in the chunk starts at or after
-// kC - m_max + 1, and a walk from the root reports every occurrence that
-// starts at or after its first byte, so each match is reported exactly once.
+// [kC, min(kC + C, n)); its walker starts from the root m_max - 1 bytes
+// before kC, rounded down to 16 (or at 0), and reports only the matches that
+// end inside the chunk. Every occurrence ending in the chunk starts at or
+// after kC - m_max + 1, and a walk from the root reports every occurrence
+// that starts at or after its first byte, so each match is reported exactly
+// once.
 //
 // Each lane runs K walkers on K different chunks in lockstep, so K table
-// lookups are in flight per lane per step. Text arrives in 16-byte groups
-// that are prefetched two groups ahead. A walker only ORs the final-state
-// flags of a group together; a flagged group is walked again and reported
-// (final states are rare next to plain steps).
+// lookups are in flight per lane per step. Each walker holds its text in
+// registers, a block of 64 or 128 bytes at a time (the next block is read as
+// the current one is walked, or in a second buffer). A walker only notes
+// whether a 16-byte group passed a final state; a flagged group is walked
+// again and reported (final states are rare next to plain steps).
 //
 // Table placements:
 //   LDS_FULL  the whole 32-bit table in LDS.
 //   LDS_HOT   16-bit rows of the hot states [0, H) in LDS; a state >= H is
 //             looked up in the 32-bit table in global memory (L2 resident).
+//             One offset per step addresses both tables. With two-byte rows
+//             built, a walker outside the image looks up two bytes at once.
 //   GLOBAL    every lookup from the 32-bit table in global memory.
 // Byte classes are either a bit field of the byte (small alphabets, checked
 // four bytes at a time with v_perm against the letter of each field value) or
