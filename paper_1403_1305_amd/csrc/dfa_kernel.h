@@ -303,20 +303,43 @@ struct Walkers {
 #pragma unroll
                     for (int k = 0; k < K; ++k)
                         g[k] = *reinterpret_cast<const uint32_t *>(tab + (s[k] >= a.hot ? u[k] << 1 : 0u));
+                    // every lane issues its load (kept out of a branch on the
+                    // lane's own state, which measured slower; no code)
+#pragma unroll
+                    for (int k = 0; k < K; ++k) asm volatile("" ::"v"(g[k]));
+                    // Every final state is outside the image, so a walker that
+                    // entered one at byte j-1 is here: its matches are reported
+                    // at once (no second walk of the group).
+                    bool fin[K];
+                    bool any_fin = false;
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const bool ck = s[k] >= a.hot;
-                        // a state outside the image entered at byte j-1 may be final
-                        if (j > 0 && ck && s[k] < a.acc_end) flag[k] |= kAccept;
+                        fin[k] = s[k] - a.hot < a.acc_end - a.hot;  // final (and so outside the image)
+                        any_fin |= fin[k];
                         e[k] = ck ? (g[k] & kStateMask) : e[k];
+                    }
+                    if (j > 0 && __builtin_expect(__any(any_fin), 0)) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const uint32_t p = gpos[k] + uint32_t(j - 1);
+                            const bool has = fin[k] && live[k] && p >= own[k];
+                            if (__any(has)) emit_set(em, has, s[k], a.base + p, a.out_off, a.out_ids);
+                        }
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k) s[k] = e[k];
             }
+            // the state after byte 15
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (s[k] - a.hot < a.acc_end - a.hot) flag[k] |= kAccept;
+            for (int k = 0; k < K; ++k) {
+                const bool fin = s[k] - a.hot < a.acc_end - a.hot;
+                if (__builtin_expect(__any(fin), 0)) {
+                    const bool has = fin && live[k] && gpos[k] + 15u >= own[k];
+                    if (__any(has)) emit_set(em, has, s[k], a.base + gpos[k] + 15u, a.out_off, a.out_ids);
+                }
+            }
         } else if constexpr (HASHED) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
