@@ -23,7 +23,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function", f"-I{ROOT}/include"]
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", f"-I{ROOT}/include"]
 
-HIP_SOURCES = ["dfa_place_hot.hip", "dfa_place_hot_pair.hip", "dfa_place_full.hip", "dfa_place_global.hip", "dfa_batch_hot.hip",
+HIP_SOURCES = ["dfa_place_hot.hip", "dfa_place_hot_k2.hip", "dfa_place_hot_k3.hip", "dfa_place_hot_k4.hip",
+               "dfa_batch_hot_k2.hip", "dfa_batch_hot_k3.hip", "dfa_batch_hot_k4.hip", "dfa_place_hot_pair.hip", "dfa_place_full.hip", "dfa_place_global.hip", "dfa_batch_hot.hip",
                "dfa_batch_global.hip", "dfa_served_hot.hip", "dfa_served_global.hip", "dfa.hip", "batch.hip", "serve.hip",
                "scan.hip", "api.hip"]
 CXX_SOURCES = ["machine.cpp"]

@@ -6,7 +6,14 @@ namespace acm {
 namespace dfa {
 
 BatchKernel select_batch_hot(bool hashed, int l2, uint32_t K, uint32_t block_bytes) {
-    return select_batch_for<AC_PLACE_LDS_HOT>(hashed, l2, K, block_bytes);
+    // two to four walkers are instantiated in dfa_batch_hot_k*.hip
+    switch (K) {
+        case 1: return select_batch_for<AC_PLACE_LDS_HOT, 1>(hashed, l2, 1, block_bytes);
+        case 2: return select_batch_hot_k2(hashed, l2, block_bytes);
+        case 3: return select_batch_hot_k3(hashed, l2, block_bytes);
+        case 4: return select_batch_hot_k4(hashed, l2, block_bytes);
+    }
+    return nullptr;
 }
 
 }  // namespace dfa

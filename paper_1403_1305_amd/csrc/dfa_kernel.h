@@ -744,8 +744,10 @@ using DfaKernel = void (*)(DfaArgs);
 // Kernel for one walker count, block size and class scheme of a placement.
 // One or two walkers: 128-byte blocks in one buffer, or 64-byte blocks in two;
 // three or four walkers: 64-byte blocks in one buffer (the registers for
-// longer blocks would spill).
-template <int PLACE>
+// longer blocks would spill). ONLY_K != 0 instantiates that walker count
+// only (the image kernels are split over translation units by walker count,
+// which compile in parallel).
+template <int PLACE, int ONLY_K = 0>
 DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) {
     const bool hashed = dm.hashed;
     const int l2 = hashed ? int(dm.log2_cols) : -1;
@@ -753,10 +755,12 @@ DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) 
 #define AC_DFA_V(KK, LL, HH, NB, GG)                                                                \
     return dfa_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
 #define AC_DFA_CASE(KK, LL, HH)                                                                     \
-    if (K == KK && l2 == LL && hashed == HH) {                                                      \
-        if constexpr (KK >= 3) { AC_DFA_V(KK, LL, HH, 1, 4) }                                       \
-        else if (block_bytes == 128) { AC_DFA_V(KK, LL, HH, 1, 8) }                                 \
-        else { AC_DFA_V(KK, LL, HH, 2, 4) }                                                         \
+    if constexpr (ONLY_K == 0 || ONLY_K == KK) {                                                    \
+        if (K == KK && l2 == LL && hashed == HH) {                                                  \
+            if constexpr (KK >= 3) { AC_DFA_V(KK, LL, HH, 1, 4) }                                   \
+            else if (block_bytes == 128) { AC_DFA_V(KK, LL, HH, 1, 8) }                             \
+            else { AC_DFA_V(KK, LL, HH, 2, 4) }                                                     \
+        }                                                                                           \
     }
 #define AC_DFA_KS(LL, HH) \
     AC_DFA_CASE(1, LL, HH) AC_DFA_CASE(2, LL, HH) AC_DFA_CASE(3, LL, HH) AC_DFA_CASE(4, LL, HH)
@@ -775,16 +779,19 @@ using BatchKernel = void (*)(BatchArgs);
 using ServedKernel = void (*)(ServedArgs);
 
 // Batch kernel for a placement (LDS_HOT or GLOBAL), walker count, block size
-// and class scheme (shared by every automaton of the batch).
-template <int PLACE>
+// and class scheme (shared by every automaton of the batch); ONLY_K as for
+// select_for.
+template <int PLACE, int ONLY_K = 0>
 BatchKernel select_batch_for(bool hashed, int l2, uint32_t K, uint32_t block_bytes) {
     constexpr bool kHot = PLACE == AC_PLACE_LDS_HOT;
 #define AC_B_V(KK, LL, HH, NB, GG)                                                                  \
     return batch_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
 #define AC_B_CASE(KK, LL, HH)                                                                       \
-    if (K == KK && l2 == LL && hashed == HH) {                                                      \
-        if constexpr (KK >= 3) { AC_B_V(KK, LL, HH, 1, 4) }                                         \
-        else { AC_B_V(KK, LL, HH, 1, 8) }                                                           \
+    if constexpr (ONLY_K == 0 || ONLY_K == KK) {                                                    \
+        if (K == KK && l2 == LL && hashed == HH) {                                                  \
+            if constexpr (KK >= 3) { AC_B_V(KK, LL, HH, 1, 4) }                                     \
+            else { AC_B_V(KK, LL, HH, 1, 8) }                                                       \
+        }                                                                                           \
     }
 #define AC_B_KS(LL, HH) AC_B_CASE(1, LL, HH) AC_B_CASE(2, LL, HH) AC_B_CASE(3, LL, HH) AC_B_CASE(4, LL, HH)
     AC_B_KS(-1, false)
@@ -798,16 +805,19 @@ BatchKernel select_batch_for(bool hashed, int l2, uint32_t K, uint32_t block_byt
     return nullptr;
 }
 
-// Served kernel for a placement, walker count, block size and class scheme.
-template <int PLACE>
+// Served kernel for a placement, walker count, block size and class scheme;
+// ONLY_K as for select_for.
+template <int PLACE, int ONLY_K = 0>
 ServedKernel select_served_for(bool hashed, int l2, uint32_t K, uint32_t block_bytes) {
     constexpr bool kHot = PLACE == AC_PLACE_LDS_HOT;
 #define AC_S_V(KK, LL, HH, NB, GG)                                                                  \
     return served_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
 #define AC_S_CASE(KK, LL, HH)                                                                       \
-    if (K == KK && l2 == LL && hashed == HH) {                                                      \
-        if constexpr (KK >= 3) { AC_S_V(KK, LL, HH, 1, 4) }                                         \
-        else { AC_S_V(KK, LL, HH, 1, 8) }                                                           \
+    if constexpr (ONLY_K == 0 || ONLY_K == KK) {                                                    \
+        if (K == KK && l2 == LL && hashed == HH) {                                                  \
+            if constexpr (KK >= 3) { AC_S_V(KK, LL, HH, 1, 4) }                                     \
+            else { AC_S_V(KK, LL, HH, 1, 8) }                                                       \
+        }                                                                                           \
     }
 #define AC_S_KS(LL, HH) AC_S_CASE(1, LL, HH) AC_S_CASE(2, LL, HH) AC_S_CASE(3, LL, HH) AC_S_CASE(4, LL, HH)
     AC_S_KS(-1, false)
@@ -829,6 +839,13 @@ ServedKernel select_served_global(bool hashed, int l2, uint32_t K, uint32_t bloc
 DfaKernel select_global(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 DfaKernel select_full(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 DfaKernel select_hot(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
+// select_hot for two, three and four walkers (translation units of their own)
+DfaKernel select_hot_k2(const DeviceMachine &dm, uint32_t block_bytes);
+DfaKernel select_hot_k3(const DeviceMachine &dm, uint32_t block_bytes);
+DfaKernel select_hot_k4(const DeviceMachine &dm, uint32_t block_bytes);
+BatchKernel select_batch_hot_k2(bool hashed, int l2, uint32_t block_bytes);
+BatchKernel select_batch_hot_k3(bool hashed, int l2, uint32_t block_bytes);
+BatchKernel select_batch_hot_k4(bool hashed, int l2, uint32_t block_bytes);
 // LDS_HOT with two-byte rows (four hashed columns); nullptr for other machines.
 DfaKernel select_hot_pair(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 
