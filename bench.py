@@ -542,6 +542,24 @@ def main():
               "matches": int(count.item()), "planted_10pct_kernel_ms_median": round(kernel_ms_median, 4),
               "ratio": round(float(np.median(ms0)) / kernel_ms_median, 3)}
         del a0
+        # the same machine over an unrelated text of the same size: only the
+        # number of matches differs from the timed steps
+        from synth import dna_text
+        other = torch.from_numpy(dna_text(n, 1000 + w.cfg + 17)).to("cuda")
+        others = [other, other.clone(), other.clone()]
+        del other
+        for i in range(2):
+            ac.ac_scan(auto, others[i % 3], n, outs, cap, count, opts, stream)
+        _, ms1 = time_steps(lambda i: ac.ac_scan(auto, others[i % 3], n, outs, cap, count, opts, stream),
+                            10, stream, torch)
+        e1["same_machine_unrelated_text"] = {
+            "kernel_ms_median": round(float(np.median(ms1)), 4), "matches": int(count.item()),
+            "ratio": round(float(np.median(ms1)) / kernel_ms_median, 3)}
+        del others
+        # the timed text again, after the two runs above (drift of the device's clocks)
+        _, ms2 = time_steps(lambda i: ac.ac_scan(auto, copies[i % 3], n, outs, cap, count, opts, stream),
+                            10, stream, torch)
+        e1["timed_text_again_kernel_ms_median"] = round(float(np.median(ms2)), 4)
 
     if args.calib_copy:
         dst = torch.empty_like(copies[0])
