@@ -51,30 +51,52 @@ def time_steps(fn, steps, stream, torch):
     return wall, ms
 
 
-KERNEL_SOURCES = ["paper_1403_1305_amd/csrc/dfa_kernel.h", "paper_1403_1305_amd/csrc/device_common.h",
-                  "paper_1403_1305_amd/csrc/dfa.hip"]
-PROFILE = os.path.join(ROOT, "profiles", "dfa_scan_dna256m.md")
+# per scan kernel: its rocprofv3 counter summary and the sources it is built from
+PROFILES = {
+    "dfa": ("dfa_scan_dna256m.md", ["paper_1403_1305_amd/csrc/dfa_kernel.h",
+                                    "paper_1403_1305_amd/csrc/device_common.h",
+                                    "paper_1403_1305_amd/csrc/dfa.hip"]),
+    "gated": ("gate_scan_dna256m.md", ["paper_1403_1305_amd/csrc/gate.hip",
+                                       "paper_1403_1305_amd/csrc/device_common.h"]),
+}
+ALGOS = {"auto": 0, "dfa": 1, "pfac": 2, "gated": 3}
+ALGO_NAMES = {1: "dfa", 2: "pfac", 3: "gated"}
 
 
-def profiled_traffic(workload):
+def kernel_source_sha256(kind):
+    import hashlib
+    h = hashlib.sha256()
+    for f in PROFILES[kind][1]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload, kind):
     """HBM bytes per scan launch from the committed rocprofv3 counter summary,
     or None when the summary is for another workload or the kernel sources
     have changed since the counters were taken."""
-    import hashlib
-    if workload != "dna256m" or not os.path.exists(PROFILE):
+    path = os.path.join(ROOT, "profiles", PROFILES[kind][0]) if kind in PROFILES else ""
+    if workload != "dna256m" or not os.path.exists(path):
         return None
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
     fields = {}
-    for line in open(PROFILE):
+    for line in open(path):
         if ":" in line and not line.startswith(("|", "#", " ")):
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != h.hexdigest():
+    if fields.get("kernel_source_sha256") != kernel_source_sha256(kind):
         return None
     return int(fields["traffic_bytes_per_launch"])
+
+
+def resolved_algo(ac, auto, algo):
+    """The matcher ac_scan runs for `algo` (AUTO resolved as the library does)."""
+    if algo != 0:
+        return algo
+    info = ac.ac_info(auto)
+    if info["has_gate"] and info["gate_pass"] <= 0.05:
+        return 3
+    return 2 if info["goto_only"] else 1
 
 
 def cpu_baseline(w, sample_bytes, min_s=10.0, max_passes=3):
@@ -407,6 +429,9 @@ def main():
     p.add_argument("--cpu-sample-mib", type=int, default=256)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-pfac", action="store_true")
+    p.add_argument("--no-dfa", action="store_true", help="skip the DFA timing beside a gated headline")
+    p.add_argument("--algo", default="auto", choices=sorted(ALGOS),
+                   help="headline matcher (auto: the one ac_scan picks by default)")
     p.add_argument("--walkers", type=int, default=0)
     p.add_argument("--calib-copy", action="store_true",
                    help="also run one plain device copy of the text's size (the reference "
@@ -481,7 +506,10 @@ def main():
     cap = 1 << 24
     outs = torch.empty(cap, dtype=torch.int64, device="cuda")
     count = torch.zeros(1, dtype=torch.int64, device="cuda")
-    opts = ac._scan_opts(ac.AC_ALGO_DFA, args.chunk, 0, args.placement, args.walkers)
+    algo = resolved_algo(ac, auto, ALGOS[args.algo])
+    kind = ALGO_NAMES[algo]
+    opts = ac._scan_opts(algo, args.chunk, 0, args.placement, args.walkers)
+    log("headline matcher", kind)
 
     def step(i):
         t = copies[i % 3]
@@ -490,9 +518,19 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    log("timed dfa")
+    log("timed", kind)
     wall, ms = time_steps(step, args.steps, stream, torch)
     matches = int(count.item())
+    # the timed list against the oracle's digest of this workload
+    golden_ok = None
+    gpath = os.path.join(ROOT, "tests", "golden", args.workload + ".json")
+    if os.path.exists(gpath) and matches <= cap:
+        import hashlib
+        g = json.load(open(gpath))
+        got = np.sort(ac.keys_to_numpy(outs[:matches]))
+        golden_ok = bool(got.size == g["count"] and
+                         hashlib.sha256(np.ascontiguousarray(got, dtype="<u8").tobytes()).hexdigest() == g["sha256"])
+        del got
     kernel_ms = float(np.mean(ms))
     value = n * args.steps / wall / 1e9
     algo_bytes = n + 8 * matches
@@ -508,6 +546,19 @@ def main():
         _, sms = time_steps(lambda i: ac.ac_sort_matches(keys, keys.numel(), tmp, tmp.numel(), stream),
                             3, stream, torch)
         sort_ms = round(float(np.median(sms)), 4)
+
+    # the chunked full-DFA walk over the same text, when it is not the headline
+    dfa = None
+    if kind != "dfa" and not args.no_dfa:
+        dopts = ac._scan_opts(ac.AC_ALGO_DFA, args.chunk, 0, args.placement, args.walkers)
+        dstep = lambda i: ac.ac_scan(auto, copies[i % 3], n, outs, cap, count, dopts, stream)
+        for i in range(2):
+            dstep(i)
+        log("timed dfa")
+        dwall, dms = time_steps(dstep, max(5, args.steps // 2), stream, torch)
+        dfa = {"value": round(n * len(dms) / dwall / 1e9, 3), "unit": "GB/s",
+               "kernel_ms": round(float(np.mean(dms)), 4), "kernel_ms_median": round(float(np.median(dms)), 4),
+               "matches": int(count.item()), "traffic": profiled_traffic(args.workload, "dfa")}
 
     pfac = None
     if not args.no_pfac:
@@ -602,12 +653,14 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
                    "n_bytes": n, "n_patterns": len(w.patterns), "states": info["n_states"],
                    "placement": info["placement"], "hot_states": info["hot_states"],
-                   "chunk": args.chunk or "auto", "kernel": "dfa_scan"},
+                   "chunk": args.chunk or "auto", "kernel": f"{kind}_scan",
+                   "gate_pass": round(info["gate_pass"], 5)},
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "matches": matches,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(args.workload)},
+                     "traffic": profiled_traffic(args.workload, kind)},
+        "exact_vs_oracle_digest": golden_ok,
         "kernel_ms": round(kernel_ms, 4),
         "kernel_ms_median": round(kernel_ms_median, 4),
         "hbm_read_ceiling": {"value": round(read_gbs, 1), "unit": "GB/s",
@@ -617,6 +670,7 @@ def main():
         "build_ms": round(info["build_ms"], 2),
         "build_upload_ms": round(build_wall_ms, 2),
         "sort_ms": sort_ms,
+        "dfa": dfa,
         "pfac": pfac,
         "cpu_baseline": cpu,
         "cpu_all_cores": cpu_all,

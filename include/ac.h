@@ -49,11 +49,21 @@ enum {
     AC_PLACE_LDS_HOT = 3   /* 16-bit rows of the most visited states in LDS, rest global */
 };
 
-/* Which device matcher a scan runs. */
+/* Which device matcher a scan runs. Every one reports the same matches. */
 enum {
-    AC_ALGO_DFA = 0, /* failure transitions folded into a full DFA, walked over
-                        overlapping chunks of the text */
-    AC_ALGO_PFAC = 1 /* failure-less machine, one walk per start position */
+    AC_ALGO_AUTO = 0,  /* GATED when the automaton has a start-position gate that
+                          passes at most 1 window code in 20, else DFA (PFAC for
+                          a goto-only automaton) */
+    AC_ALGO_DFA = 1,   /* failure transitions folded into a full DFA, walked over
+                          overlapping chunks of the text */
+    AC_ALGO_PFAC = 2,  /* failure-less machine, one walk per start position */
+    AC_ALGO_GATED = 3  /* failure-less machine, walked only from the start
+                          positions whose next 10 bytes can begin a pattern:
+                          a bitmap over the 4^10 class strings of 10 bytes,
+                          held in LDS, decides, and a table over them takes
+                          the walk's first 10 steps at once (automata whose
+                          patterns use at most four letters told apart by a
+                          2-bit field of the byte; ac_info_t.gate_pass) */
 };
 
 typedef struct ac_automaton ac_automaton;
@@ -74,14 +84,18 @@ enum {
     /* Failure-less machine only (Sec. II.B): the goto function and the
      * patterns ending at each state, without failure function, output unions
      * or full DFA. Cheaper to build (Sec. IV.A, the cost the paper reduces);
-     * such an automaton scans with AC_ALGO_PFAC only. */
+     * such an automaton scans with AC_ALGO_PFAC or AC_ALGO_GATED only. */
     AC_BUILD_GOTO_ONLY = 1,
     /* Also build two-byte rows for the states outside the LDS_HOT image
      * (4-column hashed machines with an image and at most 2^20 such states):
      * a DFA scan then looks up two bytes at once from those states. Halves
      * the dependent global lookups, but the rows are 16 times the one-byte
      * rows and miss L2 more often, so it is off by default. */
-    AC_BUILD_PAIR_ROWS = 2
+    AC_BUILD_PAIR_ROWS = 2,
+    /* Do not build the start-position gate of AC_ALGO_GATED (4 MiB of device
+     * tables and a walk of the goto function to depth 10; built by default
+     * where it applies). */
+    AC_BUILD_NO_GATE = 4
 };
 
 typedef struct {
@@ -100,6 +114,10 @@ typedef struct {
     uint32_t goto_only;    /* 1 if built with AC_BUILD_GOTO_ONLY */
     uint32_t pair_states;  /* states outside the LDS_HOT image with two-byte rows
                               (built with AC_BUILD_PAIR_ROWS); 0 if none */
+    uint32_t has_gate;     /* 1 if the start-position gate of AC_ALGO_GATED was built */
+    double gate_pass;      /* fraction of the 4^10 window class strings that the gate
+                              passes (1.0 without a gate): the share of start
+                              positions of uniformly random text that are walked */
 } ac_info_t;
 
 /*
@@ -143,9 +161,19 @@ enum {
                              odd): DFA rows of the LDS image, successor | 1<<15 if final */
     AC_TABLE_HOT_GO = 7,  /* uint16 [hot_states][n_cols]: goto rows of the LDS image */
     AC_TABLE_CMAP = 8,    /* uint8 [256]: byte -> column, 255 = byte in no pattern */
-    AC_TABLE_PAIR = 9     /* uint32 [pair_states][16]: row s - hot_states, column
+    AC_TABLE_PAIR = 9,    /* uint32 [pair_states][16]: row s - hot_states, column
                              c1 | c2 << 2 = state after classes c1, c2 from s,
                              | 1<<31 if the state after c1 is final (empty if none) */
+    AC_TABLE_GATE_BITS = 10, /* uint32 [2^15]: bit x (word x >> 5, bit x & 31) is set
+                                when a pattern can begin with a 10-byte window whose
+                                classes, first byte in the lowest 2 bits, read x
+                                (empty without a gate) */
+    AC_TABLE_GATE_NODE = 11, /* uint32 [2^20]: per window code, the deepest goto state
+                                its classes reach from the root: state | depth << 26,
+                                | 1<<31 if a pattern ends on the path to it */
+    AC_TABLE_PATH_OFF = 12,  /* uint32 [n_states+1]: patterns ending on the path from
+                                the root to s (states of depth <= 10) ... */
+    AC_TABLE_PATH_IDS = 13   /* uint32: ... in PATH_IDS[off[s] .. off[s+1]), ascending */
 };
 
 /*
@@ -165,7 +193,7 @@ void ac_free(ac_automaton *a);
 int ac_info(const ac_automaton *a, ac_info_t *info);
 
 typedef struct {
-    uint32_t algo;      /* AC_ALGO_DFA (default) or AC_ALGO_PFAC */
+    uint32_t algo;      /* AC_ALGO_* (default AUTO) */
     uint32_t chunk;     /* DFA: text bytes owned by one walker; multiple of 16;
                            0 = chosen from the text length */
     uint32_t block;     /* threads per workgroup; 0 = the placement's own (the only
@@ -191,7 +219,9 @@ enum { AC_PAIR_AUTO = 0, AC_PAIR_OFF = 1 };
  * of chunk [kC, kC + C) starts max(0, kC - m_max + 1) bytes in (rounded down
  * to 16) from the root and reports only matches ending inside its chunk, so
  * every occurrence is reported exactly once. With AC_ALGO_PFAC every start
- * position gets its own failure-less walk (Sec. II.B, Sec. IV.A).
+ * position gets its own failure-less walk (Sec. II.B, Sec. IV.A); with
+ * AC_ALGO_GATED only the start positions the gate passes do, so each
+ * occurrence is again reported once, by the walk from its first byte.
  *
  *   d_text     device, n bytes, 16-byte aligned (n == 0 allowed)
  *   d_matches  device, room for `capacity` uint64 keys

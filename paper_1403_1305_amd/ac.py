@@ -30,16 +30,20 @@ AC_PLACE_GLOBAL = 1
 AC_PLACE_LDS_FULL = 2
 AC_PLACE_LDS_HOT = 3
 
-AC_ALGO_DFA = 0
-AC_ALGO_PFAC = 1
+AC_ALGO_AUTO = 0
+AC_ALGO_DFA = 1
+AC_ALGO_PFAC = 2
+AC_ALGO_GATED = 3
 
 AC_BUILD_GOTO_ONLY = 1
 AC_BUILD_PAIR_ROWS = 2
+AC_BUILD_NO_GATE = 4
 AC_SERVE_MERGED = 2
 AC_PAIR_AUTO, AC_PAIR_OFF = 0, 1
 
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
-    AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP, AC_TABLE_PAIR = range(10)
+    AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP, AC_TABLE_PAIR, \
+    AC_TABLE_GATE_BITS, AC_TABLE_GATE_NODE, AC_TABLE_PATH_OFF, AC_TABLE_PATH_IDS = range(14)
 
 _TABLE_DTYPE = {AC_TABLE_HOT_DFA: np.uint16, AC_TABLE_HOT_GO: np.uint16, AC_TABLE_CMAP: np.uint8}
 
@@ -64,7 +68,8 @@ class ac_info_t(ctypes.Structure):
                 ("hot_states", ctypes.c_uint32), ("class_shift", ctypes.c_uint32),
                 ("class_hashed", ctypes.c_uint32), ("table_bytes", ctypes.c_uint64),
                 ("out_entries", ctypes.c_uint64), ("build_ms", ctypes.c_double),
-                ("goto_only", ctypes.c_uint32), ("pair_states", ctypes.c_uint32)]
+                ("goto_only", ctypes.c_uint32), ("pair_states", ctypes.c_uint32),
+                ("has_gate", ctypes.c_uint32), ("gate_pass", ctypes.c_double)]
 
 
 class ac_scan_opts(ctypes.Structure):

@@ -26,7 +26,7 @@ CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", f"-I{
 HIP_SOURCES = ["dfa_place_hot.hip", "dfa_place_hot_k2.hip", "dfa_place_hot_k3.hip", "dfa_place_hot_k4.hip",
                "dfa_batch_hot_k2.hip", "dfa_batch_hot_k3.hip", "dfa_batch_hot_k4.hip", "dfa_place_hot_pair.hip", "dfa_place_full.hip", "dfa_place_global.hip", "dfa_batch_hot.hip",
                "dfa_batch_global.hip", "dfa_served_hot.hip", "dfa_served_global.hip", "dfa.hip", "batch.hip", "serve.hip",
-               "scan.hip", "api.hip"]
+               "scan.hip", "gate.hip", "api.hip"]
 CXX_SOURCES = ["machine.cpp"]
 
 
@@ -37,27 +37,39 @@ def _run(cmd):
     return r.stderr
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src: str, out: str) -> bool:
+    """True unless `out` is newer than `src` and every header it may include."""
+    if not os.path.exists(out):
+        return True
+    t = os.path.getmtime(out)
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "ac.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (only the stale ones with `incremental`) and link."""
     os.makedirs(OBJ, exist_ok=True)
     jobs = []
     for src in HIP_SOURCES:
         out = os.path.join(OBJ, src + ".o")
-        jobs.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", out], out))
+        jobs.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", out], out, src))
     for src in CXX_SOURCES:
         out = os.path.join(OBJ, src + ".o")
-        jobs.append((["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", out], out))
-    with cf.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
-        logs = list(ex.map(lambda j: _run(j[0]), jobs))
+        jobs.append((["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", out], out, src))
+    todo = [j for j in jobs if not incremental or _stale(os.path.join(CSRC, j[2]), j[1])]
+    with cf.ThreadPoolExecutor(max_workers=max(1, len(todo))) as ex:
+        logs = list(ex.map(lambda j: _run(j[0]), todo))
     if verbose:
         for log in logs:
             if log.strip():
                 print(log, file=sys.stderr)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
-          *[o for _, o in jobs]])
+          *[o for _, o, _ in jobs]])
     os.replace(tmp, LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

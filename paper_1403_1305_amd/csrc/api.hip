@@ -84,7 +84,8 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
     const uint32_t place = opts ? opts->placement : AC_PLACE_AUTO;
     if (place > AC_PLACE_LDS_HOT) return fail(AC_ERR_INVALID, "ac_build: unknown placement");
     const uint32_t flags = opts ? opts->flags : 0u;
-    if (flags & ~uint32_t(AC_BUILD_GOTO_ONLY | AC_BUILD_PAIR_ROWS)) return fail(AC_ERR_INVALID, "ac_build: unknown flags");
+    if (flags & ~uint32_t(AC_BUILD_GOTO_ONLY | AC_BUILD_PAIR_ROWS | AC_BUILD_NO_GATE))
+        return fail(AC_ERR_INVALID, "ac_build: unknown flags");
     a = new (std::nothrow) ac_automaton();
     if (!a) return fail(AC_ERR_NOMEM, "ac_build: out of host memory");
     const uint32_t budget = lds_budget(opts);
@@ -96,6 +97,7 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
     }
     plan.goto_only = (flags & AC_BUILD_GOTO_ONLY) != 0;
     plan.pair_rows = (flags & AC_BUILD_PAIR_ROWS) != 0;
+    plan.gate = (flags & AC_BUILD_NO_GATE) == 0;
     plan.threads = opts ? opts->threads : 0u;
     std::string err;
     int rc;
@@ -126,6 +128,15 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
         a->placement = place;
     if (a->placement == AC_PLACE_LDS_HOT && a->m.hot_states == 0) a->placement = AC_PLACE_GLOBAL;
     return AC_OK;
+}
+
+// The matcher AC_ALGO_AUTO runs: the gated failure-less scan where its gate
+// passes few enough start positions that walking them costs less than the
+// DFA's lookup per byte, else the DFA (the failure-less scan without DFA).
+constexpr double kGateAutoPass = 0.05;
+uint32_t auto_algo(const ac_automaton *a) {
+    if (a->dm.gate_bits && a->m.gate_pass <= kGateAutoPass) return AC_ALGO_GATED;
+    return a->m.goto_only ? AC_ALGO_PFAC : AC_ALGO_DFA;
 }
 
 bool resolve_placement(const ac_automaton *a, uint32_t want, uint32_t &place) {
@@ -171,12 +182,15 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
     dm.hashed = m.hashed;
     dm.hash_shift = m.hash_shift;
     std::memcpy(dm.hash_letter, m.hash_letter, sizeof(dm.hash_letter));
+    dm.gate_pass = m.gate_pass;
     std::vector<uint8_t> cmap(m.cmap, m.cmap + 256);
     if ((rc = upload_dfa(a, m, dm, s)) || (rc = upload(a, m.go, &dm.go, s)) ||
         (rc = upload(a, m.out_off, &dm.out_off, s)) || (rc = upload(a, m.out_ids, &dm.out_ids, s)) ||
         (rc = upload(a, m.own_off, &dm.own_off, s)) || (rc = upload(a, m.own_ids, &dm.own_ids, s)) ||
         (rc = upload(a, m.hot_dfa, &dm.hot_dfa, s)) || (rc = upload(a, m.hot_go, &dm.hot_go, s)) ||
-        (rc = upload(a, cmap, &dm.cmap, s))) {
+        (rc = upload(a, cmap, &dm.cmap, s)) || (rc = upload(a, m.gate_bits, &dm.gate_bits, s)) ||
+        (rc = upload(a, m.gate_node, &dm.gate_node, s)) || (rc = upload(a, m.path_off, &dm.path_off, s)) ||
+        (rc = upload(a, m.path_ids, &dm.path_ids, s)) || (rc = upload(a, m.pat_len, &dm.pat_len, s))) {
         (void)hipStreamSynchronize(s);
         release(a);
         delete a;
@@ -226,6 +240,8 @@ int ac_info(const ac_automaton *a, ac_info_t *info) {
     info->pair_states = a->m.pair_states;
     info->out_entries = a->m.out_ids.size();
     info->build_ms = a->m.build_ms;
+    info->has_gate = a->m.gate_bits.empty() ? 0u : 1u;
+    info->gate_pass = a->m.gate_pass;
     return AC_OK;
 }
 
@@ -246,6 +262,10 @@ int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_
         case AC_TABLE_HOT_GO: src = m.hot_go.data(); sz = m.hot_go.size() * 2; break;
         case AC_TABLE_CMAP: src = m.cmap; sz = 256; break;
         case AC_TABLE_PAIR: src = m.pair.data(); sz = m.pair.size() * 4; break;
+        case AC_TABLE_GATE_BITS: src = m.gate_bits.data(); sz = m.gate_bits.size() * 4; break;
+        case AC_TABLE_GATE_NODE: src = m.gate_node.data(); sz = m.gate_node.size() * 4; break;
+        case AC_TABLE_PATH_OFF: src = m.path_off.data(); sz = m.path_off.size() * 4; break;
+        case AC_TABLE_PATH_IDS: src = m.path_ids.data(); sz = m.path_ids.size() * 4; break;
         default: return fail(AC_ERR_INVALID, "ac_get_table: unknown table");
     }
     *bytes = sz;
@@ -276,9 +296,12 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         want = opts->placement;
         if (opts->pair_steps > AC_PAIR_OFF) return fail(AC_ERR_INVALID, "ac_scan: unknown pair_steps");
     }
-    if (cfg.algo > AC_ALGO_PFAC) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
+    if (cfg.algo > AC_ALGO_GATED) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
+    if (cfg.algo == AC_ALGO_AUTO) cfg.algo = auto_algo(a);
     if (cfg.algo == AC_ALGO_DFA && a->m.goto_only)
-        return fail(AC_ERR_INVALID, "ac_scan: a goto-only automaton scans with AC_ALGO_PFAC only");
+        return fail(AC_ERR_INVALID, "ac_scan: a goto-only automaton has no DFA (use AC_ALGO_PFAC or AC_ALGO_GATED)");
+    if (cfg.algo == AC_ALGO_GATED && !a->dm.gate_bits)
+        return fail(AC_ERR_INVALID, "ac_scan: this automaton has no start-position gate (AC_ALGO_GATED)");
     if (!resolve_placement(a, want, cfg.placement))
         return fail(AC_ERR_INVALID, "ac_scan: placement not available for this automaton");
     int dev = -1;
@@ -287,9 +310,12 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
     std::string err;
     int rc = acm::launch_zero_count(d_count, s, err);
     if (rc == AC_OK) {
-        rc = cfg.algo == AC_ALGO_DFA
-                 ? acm::launch_dfa_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err)
-                 : acm::launch_pfac_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
+        if (cfg.algo == AC_ALGO_DFA)
+            rc = acm::launch_dfa_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
+        else if (cfg.algo == AC_ALGO_GATED)
+            rc = acm::launch_gate_scan(a->dm, d_text, n, d_matches, capacity, d_count, s, err);
+        else
+            rc = acm::launch_pfac_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
     }
     return rc == AC_OK ? AC_OK : fail(rc, err);
 }
@@ -312,7 +338,7 @@ int ac_scan_stream(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uin
     acm::ScanConfig cfg;
     uint32_t want = AC_PLACE_AUTO;
     if (opts) {
-        if (opts->algo != AC_ALGO_DFA)
+        if (opts->algo != AC_ALGO_DFA && opts->algo != AC_ALGO_AUTO)
             return fail(AC_ERR_INVALID, "ac_scan_stream: only the DFA scan carries state");
         cfg.chunk = opts->chunk;
         cfg.block = opts->block;

@@ -92,6 +92,68 @@ void assign_classes(const bool present[256], Machine &m) {
     m.log2_cols = m.cols_pow2 ? ceil_log2(m.n_cols) : 0;
 }
 
+// Depth-first walk of the goto function below node x (depth d, window code
+// `code` so far) that fills the start-position gate: the windows whose class
+// string runs through x and then leaves the trie (or x at depth kGateQ)
+// stop at x. `path` holds the patterns ending on the path to x's parent;
+// `lists` receives (node, pattern) for every node with a non-empty path.
+void gate_visit(Machine &m, uint32_t x, uint32_t d, uint32_t code, std::vector<uint32_t> &path,
+                std::vector<std::pair<uint32_t, uint32_t>> &lists) {
+    const size_t mark = path.size();
+    for (uint32_t k = m.own_off[x]; k < m.own_off[x + 1]; ++k) path.push_back(m.own_ids[k]);
+    for (uint32_t id : path) lists.emplace_back(x, id);
+    const uint32_t entry = x | d << kGateNodeBits | (path.empty() ? 0u : kGatePathFlag);
+    if (d == kGateQ) {
+        // a pattern of kGateQ bytes or more begins with this window
+        m.gate_node[code] = entry;
+        m.gate_bits[code >> 5] |= 1u << (code & 31);
+    } else {
+        for (uint32_t c = 0; c < 4; ++c) {
+            const uint32_t cc = code | c << (2 * d);
+            const uint32_t g = m.go[size_t(x) * 4 + c];
+            if (g) {
+                gate_visit(m, g & kStateMask, d + 1, cc, path, lists);
+                continue;
+            }
+            // no edge: every window with this prefix stops at x, and can
+            // begin only the patterns that end on the path to x
+            const uint32_t span = 1u << (2 * (kGateQ - d - 1));
+            for (uint32_t e = 0; e < span; ++e) {
+                const uint32_t w = cc | e << (2 * (d + 1));
+                m.gate_node[w] = entry;
+                if (!path.empty()) m.gate_bits[w >> 5] |= 1u << (w & 31);
+            }
+        }
+    }
+    path.resize(mark);
+}
+
+// The start-position gate of a 4-column machine with bit-field classes (see
+// Machine::gate_bits), from the goto function and own outputs in final ids.
+void build_gate(Machine &m, const uint64_t *off) {
+    const uint32_t S = m.n_states, n = m.n_patterns;
+    m.pat_len.resize(n);
+    for (uint32_t k = 0; k < n; ++k) m.pat_len[k] = uint32_t(off[k + 1] - off[k]);
+    m.gate_bits.assign(kGateCodes / 32, 0u);
+    m.gate_node.assign(kGateCodes, 0u);
+    std::vector<uint32_t> path;
+    std::vector<std::pair<uint32_t, uint32_t>> lists;
+    gate_visit(m, 0, 0, 0, path, lists);
+    m.path_off.assign(size_t(S) + 1, 0u);
+    for (auto &e : lists) m.path_off[e.first + 1]++;
+    for (uint32_t s = 0; s < S; ++s) m.path_off[s + 1] += m.path_off[s];
+    m.path_ids.assign(lists.size(), 0u);
+    {
+        std::vector<uint32_t> fill(m.path_off.begin(), m.path_off.end() - 1);
+        for (auto &e : lists) m.path_ids[fill[e.first]++] = e.second;
+    }
+    for (uint32_t s = 0; s < S; ++s)
+        std::sort(m.path_ids.begin() + m.path_off[s], m.path_ids.begin() + m.path_off[s + 1]);
+    uint64_t set = 0;
+    for (uint32_t w : m.gate_bits) set += uint32_t(__builtin_popcount(w));
+    m.gate_pass = double(set) / double(kGateCodes);
+}
+
 }  // namespace
 
 int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const HotPlan &plan,
@@ -435,6 +497,13 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
             }
         });
     }
+    m.gate_bits.clear();
+    m.gate_node.clear();
+    m.path_off.clear();
+    m.path_ids.clear();
+    m.pat_len.clear();
+    m.gate_pass = 1.0;
+    if (plan.gate && m.hashed && C == 4 && S - 1 <= kGateNodeMask) build_gate(m, off);
     // 16-bit images are copied as 32-bit words: pad them to whole words
     if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);
     if (m.hot_go.size() & 1) m.hot_go.push_back(0);

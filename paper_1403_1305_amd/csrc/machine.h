@@ -29,6 +29,17 @@ constexpr uint8_t kNoClass = 0xffu;
 // (16 four-byte entries each: 64 MiB at the limit).
 constexpr uint32_t kPairMaxStates = 1u << 20;
 
+// Start-position gate (4-column machines with bit-field classes). A window
+// of kGateQ text bytes is coded as kGateQ 2-bit classes, the first byte in
+// the lowest bits: kGateCodes codes in all.
+constexpr uint32_t kGateQ = 10;
+constexpr uint32_t kGateCodes = 1u << (2 * kGateQ);
+// gate_node entries: node id in the low bits, its depth above it, and the
+// top bit set when some pattern ends on the path from the root to the node.
+constexpr uint32_t kGateNodeBits = 26;
+constexpr uint32_t kGateNodeMask = (1u << kGateNodeBits) - 1u;
+constexpr uint32_t kGatePathFlag = 0x80000000u;
+
 struct Machine {
     uint32_t n_patterns = 0;
     uint32_t m_max = 0;
@@ -70,6 +81,20 @@ struct Machine {
     // c1 is final. Empty when not built (pair_states == 0).
     std::vector<uint32_t> pair;
     uint32_t pair_states = 0;
+    // Start-position gate for the failure-less scan (empty unless built):
+    //   gate_bits  kGateCodes bits (32 per word): bit x is set when some
+    //              pattern can begin with a window of code x, i.e. x starts
+    //              with the classes of a pattern shorter than kGateQ bytes, or
+    //              x is the class string of the first kGateQ bytes of one;
+    //   gate_node  per code, the deepest goto node its class string reaches
+    //              from the root (the walk stops at the first missing edge):
+    //              node | depth << kGateNodeBits | kGatePathFlag if a pattern
+    //              ends on the path to it;
+    //   path_off, path_ids  per node of depth <= kGateQ (CSR over all states),
+    //              the patterns ending on its path from the root, ascending;
+    //   pat_len    every pattern's length.
+    std::vector<uint32_t> gate_bits, gate_node, path_off, path_ids, pat_len;
+    double gate_pass = 1.0;  // fraction of codes whose bit is set
     double build_ms = 0.0;
 };
 
@@ -84,6 +109,7 @@ struct HotPlan {
     bool goto_only = false;
     uint32_t threads = 0;        // host threads for the build, 0 = hardware threads (at most 16)
     bool pair_rows = false;      // also build Machine::pair where it applies
+    bool gate = true;            // build the start-position gate where it applies
 };
 
 // Returns 0 or a negative AC_ERR_* code with `err` set. Without an image,

@@ -24,6 +24,11 @@ struct DeviceMachine {
     // Two-byte rows (Machine::pair) live in the dfa allocation from word
     // pair_base on (a multiple of 16); pair_states == 0 when there are none.
     uint32_t pair_states = 0, pair_base = 0;
+    // Start-position gate (Machine::gate_bits and its tables); gate_bits is
+    // NULL when the machine has none.
+    const uint32_t *gate_bits = nullptr, *gate_node = nullptr;
+    const uint32_t *path_off = nullptr, *path_ids = nullptr, *pat_len = nullptr;
+    double gate_pass = 1.0;
 };
 
 struct ScanConfig {
@@ -59,6 +64,10 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
                     uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                     std::string &err, const StreamArgs &st = StreamArgs());
 int launch_copy_state(const uint32_t *in, uint32_t *out, hipStream_t stream, std::string &err);
+// Failure-less walks from the start positions the gate passes (dm.gate_bits
+// must be set).
+int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
+                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err);
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                      std::string &err);

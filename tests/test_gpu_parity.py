@@ -298,6 +298,10 @@ def test_full_dna256m_pfac():
     check_full("dna256m", algo=ac.AC_ALGO_PFAC)
 
 
+def test_full_dna256m_gated():
+    check_full("dna256m", algo=ac.AC_ALGO_GATED)
+
+
 def test_full_protein1g_dfa():
     check_full("protein1g", device_sort=True)
 

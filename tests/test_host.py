@@ -288,7 +288,7 @@ def test_goto_only_build_walks_like_the_oracle(c):
 
 def test_goto_only_rejects_dfa_uses():
     with pytest.raises(ac.AcError):
-        build_host([b"AB"], flags=4)  # unknown flag
+        build_host([b"AB"], flags=8)  # unknown flag
 
 
 @pytest.mark.parametrize("flags", [0, ac.AC_BUILD_GOTO_ONLY])
@@ -302,3 +302,82 @@ def test_threaded_build_is_identical(flags):
     for t in (ac.AC_TABLE_DFA, ac.AC_TABLE_GO, ac.AC_TABLE_OUT_OFF, ac.AC_TABLE_OUT_IDS, ac.AC_TABLE_OWN_OFF,
               ac.AC_TABLE_OWN_IDS, ac.AC_TABLE_HOT_DFA, ac.AC_TABLE_HOT_GO, ac.AC_TABLE_CMAP):
         assert np.array_equal(ac.ac_get_table(one, t), ac.ac_get_table(many, t)), t
+
+
+# ---------------------------------------------------------------- start-position gate
+
+def class_string(p: bytes, shift: int) -> np.ndarray:
+    return (np.frombuffer(p, np.uint8) >> shift) & 3
+
+
+def gate_patterns(seed: int) -> list[bytes]:
+    """DNA patterns of lengths 1-16, with duplicates and nested prefixes, so
+    that short patterns (all extensions of their class string) take part."""
+    rng = np.random.default_rng(seed)
+    a = np.frombuffer(DNA, np.uint8)
+    pats = [a[rng.integers(0, 4, int(L))].tobytes() for L in rng.integers(1, 17, 120)]
+    pats += [pats[3], pats[7][:2], pats[11] + b"ACGT", b"ACGTACGTAC", b"ACGTACGTA"]
+    return pats
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_gate_tables_match_their_definition(seed):
+    """Bit x of the gate is set exactly when some pattern can begin with a
+    10-byte window of classes x: its first 10 classes are x's, or it is
+    shorter and x begins with its classes (brute force over the patterns).
+    The node entry is the deepest goto state of x's class string, and its
+    path list holds the patterns that are prefixes of that string."""
+    pats = gate_patterns(seed)
+    a = build_host(pats)
+    info = ac.ac_info(a)
+    assert info["has_gate"] == 1 and info["class_hashed"] == 1 and info["n_cols"] == 4
+    sh = info["class_shift"]
+    Q = 10
+    expect = np.zeros(1 << (2 * Q), bool)
+    cls = [class_string(p, sh) for p in pats]
+    for c in cls:
+        L = min(len(c), Q)
+        base = int(sum(int(c[i]) << (2 * i) for i in range(L)))
+        if L == Q:
+            expect[base] = True
+        else:
+            expect[base + (np.arange(1 << (2 * (Q - L)), dtype=np.int64) << (2 * L))] = True
+    bits = ac.ac_get_table(a, ac.AC_TABLE_GATE_BITS)
+    got = np.unpackbits(bits.view(np.uint8), bitorder="little").astype(bool)
+    assert np.array_equal(got, expect)
+    assert info["gate_pass"] == pytest.approx(expect.mean())
+
+    node = ac.ac_get_table(a, ac.AC_TABLE_GATE_NODE)
+    path_off = ac.ac_get_table(a, ac.AC_TABLE_PATH_OFF)
+    path_ids = ac.ac_get_table(a, ac.AC_TABLE_PATH_IDS)
+    go = ac.ac_get_table(a, ac.AC_TABLE_GO).reshape(-1, 4)
+    rng = np.random.default_rng(seed + 100)
+    codes = np.concatenate([rng.integers(0, 1 << 20, 600), np.nonzero(expect)[0][::61]])
+    for x in codes.tolist():
+        w = [(x >> (2 * i)) & 3 for i in range(Q)]
+        # deepest prefix of w shared with some pattern, and the patterns that are prefixes of w
+        depth = max(next((i for i in range(min(len(c), Q)) if c[i] != w[i]), min(len(c), Q)) for c in cls)
+        prefix_ids = sorted(k for k, c in enumerate(cls) if len(c) <= depth and list(c) == w[:len(c)])
+        e = int(node[x])
+        assert (e >> 26) & 31 == depth, x
+        assert bool(e >> 31) == bool(prefix_ids), x
+        s = 0
+        for i in range(depth):  # the entry's state is that prefix's goto state
+            s = int(go[s, w[i]]) & 0x7FFFFFFF
+        assert e & ((1 << 26) - 1) == s, x
+        assert path_ids[path_off[s]:path_off[s + 1]].tolist() == prefix_ids, x
+
+
+def test_gate_only_where_it_applies():
+    assert ac.ac_info(build_host([b"ACGTACGTACGT"]))["has_gate"] == 1
+    assert ac.ac_info(build_host([b"ACGTACGTACGT"], flags=ac.AC_BUILD_NO_GATE))["has_gate"] == 0
+    assert ac.ac_info(build_host([b"ACGTACGTACGT"], flags=ac.AC_BUILD_GOTO_ONLY))["has_gate"] == 1
+    prot = ac.ac_info(build_host([PROTEIN[:8], PROTEIN[5:]]))
+    assert prot["has_gate"] == 0 and prot["gate_pass"] == 1.0
+    # a 3-letter alphabet in a 2-bit field: the fourth class has no letter
+    three = ac.ac_info(build_host([b"ACGACG", b"GGA"]))
+    assert three["n_cols"] == 4 and three["has_gate"] == 1
+    # the headline pattern set passes about 1% of windows
+    w = plain_workload("dna256m", n=1 << 20)
+    info = ac.ac_info(build_host(w.patterns))
+    assert info["has_gate"] == 1 and 0.005 < info["gate_pass"] < 0.02
