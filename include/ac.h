@@ -173,7 +173,11 @@ enum {
                                 | 1<<31 if a pattern ends on the path to it */
     AC_TABLE_PATH_OFF = 12,  /* uint32 [n_states+1]: patterns ending on the path from
                                 the root to s (states of depth <= 10) ... */
-    AC_TABLE_PATH_IDS = 13   /* uint32: ... in PATH_IDS[off[s] .. off[s+1]), ascending */
+    AC_TABLE_PATH_IDS = 13,  /* uint32: ... in PATH_IDS[off[s] .. off[s+1]), ascending */
+    AC_TABLE_GATE2_BITS = 14 /* uint32 [2^11]: second gate level, bit h set for
+                                h = (y * 0x9E3779B1) >> 16 (32-bit product) of every
+                                class string y of 12 bytes (first byte in the lowest
+                                2 bits) that a pattern can begin with */
 };
 
 /*

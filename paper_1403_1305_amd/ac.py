@@ -43,7 +43,8 @@ AC_PAIR_AUTO, AC_PAIR_OFF = 0, 1
 
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
     AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP, AC_TABLE_PAIR, \
-    AC_TABLE_GATE_BITS, AC_TABLE_GATE_NODE, AC_TABLE_PATH_OFF, AC_TABLE_PATH_IDS = range(14)
+    AC_TABLE_GATE_BITS, AC_TABLE_GATE_NODE, AC_TABLE_PATH_OFF, AC_TABLE_PATH_IDS, \
+    AC_TABLE_GATE2_BITS = range(15)
 
 _TABLE_DTYPE = {AC_TABLE_HOT_DFA: np.uint16, AC_TABLE_HOT_GO: np.uint16, AC_TABLE_CMAP: np.uint8}
 

@@ -188,7 +188,7 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
         (rc = upload(a, m.out_off, &dm.out_off, s)) || (rc = upload(a, m.out_ids, &dm.out_ids, s)) ||
         (rc = upload(a, m.own_off, &dm.own_off, s)) || (rc = upload(a, m.own_ids, &dm.own_ids, s)) ||
         (rc = upload(a, m.hot_dfa, &dm.hot_dfa, s)) || (rc = upload(a, m.hot_go, &dm.hot_go, s)) ||
-        (rc = upload(a, cmap, &dm.cmap, s)) || (rc = upload(a, m.gate_bits, &dm.gate_bits, s)) ||
+        (rc = upload(a, cmap, &dm.cmap, s)) || (rc = upload(a, m.gate_bits, &dm.gate_bits, s)) || (rc = upload(a, m.gate2_bits, &dm.gate2_bits, s)) ||
         (rc = upload(a, m.gate_node, &dm.gate_node, s)) || (rc = upload(a, m.path_off, &dm.path_off, s)) ||
         (rc = upload(a, m.path_ids, &dm.path_ids, s)) || (rc = upload(a, m.pat_len, &dm.pat_len, s))) {
         (void)hipStreamSynchronize(s);
@@ -266,6 +266,7 @@ int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_
         case AC_TABLE_GATE_NODE: src = m.gate_node.data(); sz = m.gate_node.size() * 4; break;
         case AC_TABLE_PATH_OFF: src = m.path_off.data(); sz = m.path_off.size() * 4; break;
         case AC_TABLE_PATH_IDS: src = m.path_ids.data(); sz = m.path_ids.size() * 4; break;
+        case AC_TABLE_GATE2_BITS: src = m.gate2_bits.data(); sz = m.gate2_bits.size() * 4; break;
         default: return fail(AC_ERR_INVALID, "ac_get_table: unknown table");
     }
     *bytes = sz;

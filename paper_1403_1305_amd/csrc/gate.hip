@@ -4,19 +4,21 @@
 // failure-less machine (the goto function with the patterns that end at each
 // state, the paper's Sec. II.B and IV.A) walked from that position finds every
 // pattern that begins there. Most positions begin no pattern at all, and the
-// next kGateQ bytes decide it: their 2-bit classes form a 20-bit code, and a
-// bitmap over every code, held in LDS, marks those some pattern can begin
-// with. Only marked positions are walked, and a table over the codes takes a
-// walk's first kGateQ steps in one lookup.
+// bytes from the position on decide it: the 2-bit classes of the next
+// kGateQ bytes form a 20-bit code, and a bitmap over every code, held in
+// LDS, marks those some pattern can begin with. A start that passes is
+// checked once more against a small hashed bitmap (also in LDS) over the
+// classes of kGateQ + 2 bytes, and only then walked; a table over the 20-bit
+// codes takes the walk's first kGateQ steps in one lookup.
 //
-// A wave takes 1 KiB of text per step, 16 bytes per lane in one coalesced
-// load. Each lane packs its bytes into one word of classes; the word of the
-// lane before (of the wave's previous step, for lane 0) supplies the 9 bytes
-// before them, so the lane tests the 16 windows that end in its bytes. Marked
-// start positions go to a per-wave queue in LDS; whenever it holds 64 the
-// whole wave walks them, one per lane. Windows and starts line up one to
-// one, so each start (and each match) is handled once, with no overlap
-// between waves beyond the 9 bytes a lane borrows from its neighbour.
+// A wave step reads 1 KiB of text, 16 bytes per lane in one coalesced load,
+// and owns the last 1008 of them: lane 0 holds the 16 bytes before, so that
+// every lane finds the 9 bytes before its own in the lane below it and tests
+// the 16 windows that end in its bytes. Steps are handed to the waves of the
+// grid in turn. Starts that pass both levels go to a per-wave queue in LDS;
+// whenever 63 or more wait, the wave walks up to 64 of them, one per lane.
+// Every start position belongs to the one window that begins at it, so each
+// occurrence is found once.
 #include <algorithm>
 
 #include "device_common.h"
@@ -29,23 +31,23 @@ namespace {
 constexpr uint32_t kGateBlock = 1024;
 constexpr uint32_t kGateWaves = kGateBlock / 64;
 constexpr uint32_t kLaneBytes = 16;
-constexpr uint32_t kTileBytes = 64 * kLaneBytes;  // text of one wave step
-constexpr uint32_t kPrefetch = 4;                 // wave steps loaded ahead
-constexpr uint32_t kStartQueue = 128;             // queued start positions per wave
+constexpr uint32_t kOwnBytes = 63 * kLaneBytes;  // text a wave step owns
+constexpr uint32_t kPrefetch = 4;                // wave steps loaded ahead
+constexpr uint32_t kStartQueue = 125;            // queued start positions per wave: 62 + 63
 constexpr uint32_t kBitmapBytes = kGateCodes / 8;
 constexpr uint32_t kBitmapWords = kGateCodes / 32;
-constexpr uint32_t kGateLds = kBitmapBytes + kGateWaves * (kStartQueue * 8 + kQueueBytesPerWave);
+constexpr uint32_t kBitmap2Words = kGate2Bits / 32;
+constexpr uint32_t kGateLds =
+    kBitmapBytes + kBitmap2Words * 4 + kGateWaves * (kStartQueue * 8 + kQueueBytesPerWave);
 static_assert(kGateLds <= kLdsPerWorkgroup, "gate kernel LDS");
-static_assert(kGateQ == 10, "the window extraction below assumes 10-byte windows");
+static_assert(kGateQ == 10 && kGateQ2 == 12, "the window extraction below assumes 10- and 12-byte windows");
 
 struct GateArgs {
     const uint8_t *text;
     uint32_t n;
-    uint32_t n_tiles;         // ceil(n / kTileBytes)
-    uint32_t tiles_per_wave;  // consecutive tiles each wave takes
     uint32_t shift;           // class of byte b = (b >> shift) & 3
     uint32_t letters;         // byte c = the letter of class c
-    const uint32_t *bits, *node, *go, *own_off, *own_ids, *path_off, *path_ids, *pat_len;
+    const uint32_t *bits, *bits2, *node, *go, *own_off, *own_ids, *path_off, *path_ids, *pat_len;
     uint64_t *out;
     uint64_t cap;
     unsigned long long *count;
@@ -63,11 +65,12 @@ __device__ __forceinline__ uint32_t pack_classes(const uint4 &v, uint32_t shift)
     return (p0 >> shift) | (p1 << (8 - shift)) | (p2 << (16 - shift)) | (p3 << (24 - shift));
 }
 
-// The 16 bytes at `pos` (16-byte aligned). A block that holds byte pos < n
-// lies on a mapped page, so it is read whole; bytes past n are never used.
-__device__ __forceinline__ uint4 load_lane(const uint8_t *text, uint32_t pos, uint32_t n) {
-    if (pos >= n) return make_uint4(0u, 0u, 0u, 0u);
-    return *reinterpret_cast<const uint4 *>(text + pos);
+// 16 bytes the text streams past once (non-temporal: they need not stay in
+// the caches, which then keep the walks' tables).
+__device__ __forceinline__ uint4 load_stream(const uint8_t *p) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(x[0], x[1], x[2], x[3]);
 }
 
 // Bytes [p, p + 12) as three words (p < n; bytes at or past n are garbage).
@@ -149,94 +152,139 @@ __device__ __forceinline__ void walk_starts(const GateArgs &a, bool has, uint32_
     walk_on(a, has && d == kGateQ && run == kGateQ, x, p + kGateQ, em);
 }
 
+// Walk up to 64 of the qn starts queued at q (entries {start, window code}),
+// one per lane; returns how many wait afterwards.
+__device__ __forceinline__ uint32_t drain_starts(const GateArgs &a, const uint2 *q, uint32_t qn, Emitter &em) {
+    const uint32_t lane = __lane_id();
+    const uint32_t took = min(qn, 64u);
+    __builtin_amdgcn_wave_barrier();
+    const uint2 e = lane < took ? q[qn - took + lane] : make_uint2(0u, 0u);
+    __builtin_amdgcn_wave_barrier();
+    walk_starts(a, lane < took, e.x, e.y, em);
+    return qn - took;
+}
+
+// The windows of one wave step. Lane l (l >= 1) owns the 16 bytes at pos and
+// holds their classes in W; P holds the lane below's (the 16 bytes before),
+// Wn the lane above's. `valid` masks the windows (by their last byte) that
+// lie inside the text. With SECOND, a window that passes the first level is
+// kept only if its 12-byte class string passes the second (where the lane
+// holds those bytes). Kept starts are queued at q (qn of them waiting, the
+// same in every lane); whenever 63 or more wait (a queue below 63 takes a
+// round's at most 63 new ones) up to 64 are walked.
+template <bool SECOND>
+__device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *s_bits, const uint32_t *s_bits2,
+                                             uint32_t W, uint32_t P, uint32_t Wn, uint32_t pos, uint32_t valid,
+                                             uint2 *q, uint32_t &qn, Emitter &em) {
+    const uint32_t lane = __lane_id();
+    // window ending at byte j of the lane: classes of bytes j-9 .. j, bits
+    // 14 + 2j on in the 64-bit word P:W
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 16; ++j) {
+        const uint32_t r = j <= 8 ? __builtin_amdgcn_alignbit(W, P, 14u + 2u * j) : (W >> (2u * j - 18u));
+        const uint32_t word = s_bits[(r >> 5) & (kBitmapWords - 1u)];
+        // bit r mod 32 of the word (the field offset takes r's low 5 bits)
+        m |= __builtin_amdgcn_ubfe(word, r, 1u) << j;
+    }
+    m &= valid;
+    while (true) {
+        const uint64_t has = __ballot(m != 0);
+        if (has == 0) break;
+        bool keep = false;
+        uint32_t p = 0, code = 0;
+        if (m) {
+            const uint32_t j = uint32_t(__builtin_ctz(m));
+            m &= m - 1u;
+            // classes of bytes j-9 .. j+6 of the lane (the window and what follows)
+            const uint32_t r = j <= 8 ? __builtin_amdgcn_alignbit(W, P, 14u + 2u * j)
+                                      : __builtin_amdgcn_alignbit(Wn, W, 2u * j - 18u);
+            code = r & (kGateCodes - 1u);
+            p = pos + j - (kGateQ - 1);
+            keep = true;
+            if (SECOND && (lane < 63 || j < 14)) {
+                const uint32_t h = gate2_hash(r & 0xffffffu);
+                keep = __builtin_amdgcn_ubfe(s_bits2[h >> 5], h, 1u) != 0u;
+            }
+        }
+        const uint64_t ks = __ballot(keep);
+        if (keep) q[qn + lane_rank(ks)] = make_uint2(p, code);
+        qn += uint32_t(__popcll(ks));
+        if (qn >= 63) qn = drain_starts(a, q, qn, em);
+    }
+}
+
 __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
-    // static LDS: the bitmap's address is then a constant the lookups fold in
+    // static LDS: the bitmaps' addresses are then constants the lookups fold in
     __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
+    __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
     __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
     __shared__ __align__(16) uint8_t s_emit[kGateWaves * kQueueBytesPerWave];
-    const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x & 63u;
-    uint2 *q = s_queue + wave * kStartQueue;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x & 63u;
     Emitter em;
     em.init(s_emit, a.out, a.cap, a.count);
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.bits);
         uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
-        for (uint32_t i = threadIdx.x; i < kBitmapBytes / 16; i += kGateBlock) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < kBitmapWords / 4; i += kGateBlock) dst[i] = src[i];
+        const uint4 *src2 = reinterpret_cast<const uint4 *>(a.bits2);
+        uint4 *dst2 = reinterpret_cast<uint4 *>(s_bits2);
+        for (uint32_t i = threadIdx.x; i < kBitmap2Words / 4; i += kGateBlock) dst2[i] = src2[i];
     }
     __syncthreads();
-
-    const uint32_t gw = blockIdx.x * kGateWaves + wave;
-    const uint32_t t0 = min(gw * a.tiles_per_wave, a.n_tiles);
-    const uint32_t t1 = min(t0 + a.tiles_per_wave, a.n_tiles);
+    uint2 *q = s_queue + wave * kStartQueue;
     uint32_t qn = 0;  // queued starts (the same in every lane)
-    if (t0 < t1) {
-        // classes of the 16 bytes before the first tile: lane 0's left neighbour
-        uint32_t carry = 0;
-        if (t0 > 0) carry = pack_classes(*reinterpret_cast<const uint4 *>(a.text + t0 * kTileBytes - 16), a.shift);
-        uint4 buf[kPrefetch];
+
+    const uint32_t W = gridDim.x * kGateWaves, gw = blockIdx.x * kGateWaves + wave;
+    const uint32_t n_tiles = uint32_t((uint64_t(a.n) + kOwnBytes - 1) / kOwnBytes);
+    // tiles whose 1 KiB lies inside the text, the first excepted (its lane 0
+    // would read before byte 0): t = first, first + W, ... < full
+    const uint32_t full = a.n / kOwnBytes;
+    const uint32_t first = gw == 0 ? W : gw;
+    const uint32_t cnt = full > first ? (full - first + W - 1) / W : 0u;
+    const uint8_t *lane_text = a.text + lane * kLaneBytes;  // + t * kOwnBytes - 16
+    uint4 buf[kPrefetch];  // the next kPrefetch tiles of this wave, in flight
 #pragma unroll
-        for (uint32_t k = 0; k < kPrefetch; ++k)
-            buf[k] = t0 + k < t1 ? load_lane(a.text, (t0 + k) * kTileBytes + lane * kLaneBytes, a.n)
-                                 : make_uint4(0u, 0u, 0u, 0u);
-        for (uint32_t t = t0; t < t1; t += kPrefetch) {
+    for (uint32_t k = 0; k < kPrefetch; ++k)
+        buf[k] = k < cnt ? load_stream(lane_text + (first + k * W) * kOwnBytes - 16) : make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t i = 0; i < cnt; i += kPrefetch) {
 #pragma unroll
-            for (uint32_t k = 0; k < kPrefetch; ++k) {
-                const uint32_t tile = t + k;
-                if (tile >= t1) break;
-                const uint4 v = buf[k];
-                const uint32_t ahead = tile + kPrefetch;
-                buf[k] = ahead < t1 ? load_lane(a.text, ahead * kTileBytes + lane * kLaneBytes, a.n)
-                                    : make_uint4(0u, 0u, 0u, 0u);
-                const uint32_t pos = tile * kTileBytes + lane * kLaneBytes;
-                const uint32_t W = pack_classes(v, a.shift);
-                const uint32_t up = __shfl_up(W, 1);
-                const uint32_t P = lane == 0 ? carry : up;
-                carry = __builtin_amdgcn_readlane(W, 63);
-                // window ending at byte j of this lane: classes of bytes j-9 .. j,
-                // bits 14 + 2j on in the 64-bit word P:W
-                uint32_t m = 0;
-#pragma unroll
-                for (uint32_t j = 0; j < 16; ++j) {
-                    const uint32_t r = j <= 8 ? __builtin_amdgcn_alignbit(W, P, 14u + 2u * j) : (W >> (2u * j - 18u));
-                    const uint32_t word = s_bits[(r >> 5) & (kBitmapWords - 1u)];
-                    // bit r mod 32 of the word (the field offset takes r's low 5 bits)
-                    m |= __builtin_amdgcn_ubfe(word, r, 1u) << j;
-                }
-                // windows must start at byte 0 or later and end before byte n
-                if (pos < kGateQ - 1) m &= 0xffffu << (kGateQ - 1 - pos);
-                if (pos + kLaneBytes > a.n) m &= pos < a.n ? (1u << (a.n - pos)) - 1u : 0u;
-                // queue the marked starts; walk 64 of them whenever that many wait
-                while (true) {
-                    const uint64_t has = __ballot(m != 0);
-                    if (has == 0) break;
-                    if (m) {
-                        const uint32_t j = uint32_t(__builtin_ctz(m));
-                        m &= m - 1u;
-                        const uint32_t r = j <= 8 ? __builtin_amdgcn_alignbit(W, P, 14u + 2u * j) : (W >> (2u * j - 18u));
-                        q[qn + lane_rank(has)] = make_uint2(pos + j - (kGateQ - 1), r & (kGateCodes - 1u));
-                    }
-                    qn += uint32_t(__popcll(has));
-                    if (qn >= 64) {
-                        __builtin_amdgcn_wave_barrier();
-                        const uint2 e = q[qn - 64 + lane];
-                        __builtin_amdgcn_wave_barrier();
-                        qn -= 64;
-                        walk_starts(a, true, e.x, e.y, em);
-                    }
-                }
-            }
+        for (uint32_t k = 0; k < kPrefetch; ++k) {
+            if (i + k >= cnt) break;
+            const uint32_t t = first + (i + k) * W;
+            const uint4 v = buf[k];
+            if (i + k + kPrefetch < cnt) buf[k] = load_stream(lane_text + (t + kPrefetch * W) * kOwnBytes - 16);
+            const uint32_t Wd = pack_classes(v, a.shift);
+            const uint32_t P = __shfl_up(Wd, 1);
+            const uint32_t Wn = __shfl_down(Wd, 1);
+            const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
+            step_windows<true>(a, s_bits, s_bits2, Wd, P, Wn, pos, lane ? 0xffffu : 0u, q, qn, em);
         }
     }
-    __builtin_amdgcn_wave_barrier();
-    {
-        const bool has = lane < qn;
-        const uint2 e = has ? q[lane] : make_uint2(0u, 0u);
-        walk_starts(a, has, e.x, e.y, em);
+    // the first tile and a last, partial one: loads and windows checked
+    // against the text's ends, second level left out
+    for (uint32_t e = 0; e < 2; ++e) {
+        const uint32_t t = e == 0 ? 0u : n_tiles - 1u;
+        if (n_tiles == 0 || (e == 1 && (t < full || t == 0)) || gw != t % W) continue;
+        const int64_t base = int64_t(t) * kOwnBytes - 16 + int64_t(lane) * kLaneBytes;
+        const uint4 v = base >= 0 && base < int64_t(a.n) ? *reinterpret_cast<const uint4 *>(a.text + base)
+                                                          : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t Wd = pack_classes(v, a.shift);
+        const uint32_t P = __shfl_up(Wd, 1);
+        const uint32_t Wn = __shfl_down(Wd, 1);
+        // window ends base + j must lie in [kGateQ - 1, n)
+        uint32_t valid = 0;
+        if (lane > 0) {
+            for (uint32_t j = 0; j < 16; ++j)
+                if (base + j >= kGateQ - 1 && base + j < int64_t(a.n)) valid |= 1u << j;
+        }
+        step_windows<false>(a, s_bits, s_bits2, Wd, P, Wn, uint32_t(base), valid, q, qn, em);
     }
+    if (qn) drain_starts(a, q, qn, em);
     // starts too close to the end for a whole window: walked from the root
-    if (blockIdx.x == 0 && wave == 0) {
-        const uint32_t first = a.n > kGateQ - 1 ? a.n - (kGateQ - 1) : 0u;
-        walk_on(a, first + lane < a.n, 0u, first + lane, em);
+    if (gw == 0) {
+        const uint32_t from = a.n > kGateQ - 1 ? a.n - (kGateQ - 1) : 0u;
+        walk_on(a, from + lane < a.n, 0u, from + lane, em);
     }
     em.flush();
 }
@@ -256,15 +304,14 @@ int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     GateArgs a{};
     a.text = text;
     a.n = uint32_t(n);
-    a.n_tiles = uint32_t((n + kTileBytes - 1) / kTileBytes);
-    // one workgroup per CU (the bitmap fills the LDS), fewer for short texts
-    const uint32_t want = (a.n_tiles + kGateWaves - 1) / kGateWaves;
-    const uint32_t grid = std::max<uint32_t>(1, std::min(want, cus));
-    a.tiles_per_wave = (a.n_tiles + grid * kGateWaves - 1) / (grid * kGateWaves);
+    // one workgroup per CU (the bitmaps fill the LDS), fewer for short texts
+    const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
+    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kGateWaves - 1) / kGateWaves, cus)));
     a.shift = dm.hash_shift;
     a.letters = uint32_t(dm.hash_letter[0]) | uint32_t(dm.hash_letter[1]) << 8 |
                 uint32_t(dm.hash_letter[2]) << 16 | uint32_t(dm.hash_letter[3]) << 24;
     a.bits = dm.gate_bits;
+    a.bits2 = dm.gate2_bits;
     a.node = dm.gate_node;
     a.go = dm.go;
     a.own_off = dm.own_off;

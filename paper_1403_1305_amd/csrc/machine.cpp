@@ -130,7 +130,7 @@ void gate_visit(Machine &m, uint32_t x, uint32_t d, uint32_t code, std::vector<u
 
 // The start-position gate of a 4-column machine with bit-field classes (see
 // Machine::gate_bits), from the goto function and own outputs in final ids.
-void build_gate(Machine &m, const uint64_t *off) {
+void build_gate(Machine &m, const uint8_t *pat, const uint64_t *off) {
     const uint32_t S = m.n_states, n = m.n_patterns;
     m.pat_len.resize(n);
     for (uint32_t k = 0; k < n; ++k) m.pat_len[k] = uint32_t(off[k + 1] - off[k]);
@@ -152,6 +152,27 @@ void build_gate(Machine &m, const uint64_t *off) {
     uint64_t set = 0;
     for (uint32_t w : m.gate_bits) set += uint32_t(__builtin_popcount(w));
     m.gate_pass = double(set) / double(kGateCodes);
+    // second level: the class strings of kGateQ2 bytes patterns begin with
+    m.gate2_bits.assign(kGate2Bits / 32, 0u);
+    uint64_t work = 0;  // class strings to hash: every extension of the short patterns
+    for (uint32_t k = 0; k < n; ++k)
+        work += m.pat_len[k] >= kGateQ2 ? 1ull : 1ull << (2 * (kGateQ2 - m.pat_len[k]));
+    if (work > 8ull * kGate2Bits) {
+        // so many short patterns that the level would pass nearly everything
+        std::fill(m.gate2_bits.begin(), m.gate2_bits.end(), ~0u);
+        return;
+    }
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint64_t len = off[k + 1] - off[k];
+        const uint32_t L = uint32_t(std::min<uint64_t>(len, kGateQ2));
+        uint32_t code = 0;
+        for (uint32_t i = 0; i < L; ++i) code |= uint32_t(m.cmap[pat[off[k] + i]]) << (2 * i);
+        const uint32_t span = 1u << (2 * (kGateQ2 - L));
+        for (uint32_t e = 0; e < span; ++e) {
+            const uint32_t h = gate2_hash(code | (L < kGateQ2 ? e << (2 * L) : 0u));
+            m.gate2_bits[h >> 5] |= 1u << (h & 31);
+        }
+    }
 }
 
 }  // namespace
@@ -498,12 +519,13 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         });
     }
     m.gate_bits.clear();
+    m.gate2_bits.clear();
     m.gate_node.clear();
     m.path_off.clear();
     m.path_ids.clear();
     m.pat_len.clear();
     m.gate_pass = 1.0;
-    if (plan.gate && m.hashed && C == 4 && S - 1 <= kGateNodeMask) build_gate(m, off);
+    if (plan.gate && m.hashed && C == 4 && S - 1 <= kGateNodeMask) build_gate(m, pat, off);
     // 16-bit images are copied as 32-bit words: pad them to whole words
     if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);
     if (m.hot_go.size() & 1) m.hot_go.push_back(0);

@@ -39,6 +39,13 @@ constexpr uint32_t kGateCodes = 1u << (2 * kGateQ);
 constexpr uint32_t kGateNodeBits = 26;
 constexpr uint32_t kGateNodeMask = (1u << kGateNodeBits) - 1u;
 constexpr uint32_t kGatePathFlag = 0x80000000u;
+// Second gate level: a bitmap of kGate2Bits bits over a hash of the classes
+// of kGateQ2 bytes (the window and the two bytes after it).
+constexpr uint32_t kGateQ2 = kGateQ + 2;
+constexpr uint32_t kGate2Bits = 1u << 16;
+// Bit of the second level for the class string code (first byte in the
+// lowest two bits): the top 16 bits of a multiplicative hash.
+inline constexpr uint32_t gate2_hash(uint32_t code24) { return (code24 * 0x9E3779B1u) >> 16; }
 
 struct Machine {
     uint32_t n_patterns = 0;
@@ -93,7 +100,10 @@ struct Machine {
     //   path_off, path_ids  per node of depth <= kGateQ (CSR over all states),
     //              the patterns ending on its path from the root, ascending;
     //   pat_len    every pattern's length.
-    std::vector<uint32_t> gate_bits, gate_node, path_off, path_ids, pat_len;
+    //   gate2_bits kGate2Bits bits: bit gate2_hash(y) is set for every class
+    //              string y of kGateQ2 bytes a pattern can begin with (its
+    //              first kGateQ2 classes, or every extension of a shorter one);
+    std::vector<uint32_t> gate_bits, gate2_bits, gate_node, path_off, path_ids, pat_len;
     double gate_pass = 1.0;  // fraction of codes whose bit is set
     double build_ms = 0.0;
 };

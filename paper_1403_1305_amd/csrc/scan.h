@@ -26,7 +26,7 @@ struct DeviceMachine {
     uint32_t pair_states = 0, pair_base = 0;
     // Start-position gate (Machine::gate_bits and its tables); gate_bits is
     // NULL when the machine has none.
-    const uint32_t *gate_bits = nullptr, *gate_node = nullptr;
+    const uint32_t *gate_bits = nullptr, *gate2_bits = nullptr, *gate_node = nullptr;
     const uint32_t *path_off = nullptr, *path_ids = nullptr, *pat_len = nullptr;
     double gate_pass = 1.0;
 };

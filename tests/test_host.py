@@ -368,6 +368,33 @@ def test_gate_tables_match_their_definition(seed):
         assert path_ids[path_off[s]:path_off[s + 1]].tolist() == prefix_ids, x
 
 
+@pytest.mark.parametrize("seed", [1, 4])
+def test_second_gate_level_passes_every_pattern_start(seed):
+    """The second level may pass strings no pattern begins with (it is a
+    hashed bitmap), but never stops one that some pattern does: the 12 classes
+    a pattern begins with, or any extension of a shorter pattern."""
+    rng = np.random.default_rng(seed)
+    a8 = np.frombuffer(DNA, np.uint8)
+    pats = [a8[rng.integers(0, 4, int(L))].tobytes() for L in rng.integers(9, 30, 400)]
+    a = build_host(pats)
+    sh = ac.ac_info(a)["class_shift"]
+    bits = np.unpackbits(ac.ac_get_table(a, ac.AC_TABLE_GATE2_BITS).view(np.uint8), bitorder="little").astype(bool)
+    assert bits.size == 1 << 16 and 0.0 < bits.mean() < 0.2
+
+    def h(y):
+        return ((y * 0x9E3779B1) & 0xFFFFFFFF) >> 16
+
+    for p in pats:
+        c = class_string(p, sh)
+        L = min(len(c), 12)
+        base = sum(int(c[i]) << (2 * i) for i in range(L))
+        for e in range(1 << (2 * (12 - L))):
+            assert bits[h(base | (e << (2 * L)))], (p, e)
+    # three 3-byte patterns extend to 3 x 4^9 strings, more than 8 per bit: the level passes all
+    everything = build_host([b"ACG", b"TTA", b"GGC"] + pats[:5])
+    assert ac.ac_get_table(everything, ac.AC_TABLE_GATE2_BITS).min() == 0xFFFFFFFF
+
+
 def test_gate_only_where_it_applies():
     assert ac.ac_info(build_host([b"ACGTACGTACGT"]))["has_gate"] == 1
     assert ac.ac_info(build_host([b"ACGTACGTACGT"], flags=ac.AC_BUILD_NO_GATE))["has_gate"] == 0
