@@ -299,8 +299,7 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     torch.cuda.empty_cache()
 
     budget = 4 << 30
-    srv = ac.Server(autos, hbm_budget=budget, max_inflight=args.slots,
-                    flags=ac.AC_SERVE_MERGED if args.serve_merged else 0)
+    srv = ac.Server(autos, hbm_budget=budget, max_inflight=args.slots)
 
     def replay(arrivals_ns):
         base = srv.now_ns() + 50_000_000  # submissions finish well before the first arrival
@@ -351,7 +350,6 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     return {
         "workload": f"served: {SERVED_DESC}", "requests": R, "text_bytes": total, "automata": len(autos),
         "slots": args.slots, "hbm_budget": budget, "piece_bytes": 16 << 20,
-        "merged": bool(args.serve_merged), "merged_launches": st["merged_launches"],
         "serial_plain": {"value": round(serial_gbs, 3), "unit": "GB/s", "ms": round(serial_ms, 3)},
         "saturated": sat, "poisson": poisson,
         "exact_vs_plain": exact, "pool_peak": st["pool_peak"], "build_s": round(build_s, 2),
@@ -415,15 +413,10 @@ def main():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="dna256m", choices=sorted(WORKLOAD_DESC) + ["batched", "served", "build"])
     p.add_argument("--no-batched", action="store_true", help="skip the batched sub-benchmark")
-    p.add_argument("--no-served", action="store_true", help="(default) skip the served sub-benchmark")
-    p.add_argument("--served", action="store_true",
-                   help="add the served sub-benchmark to the headline run (off by default: one of its "
-                        "Poisson replays once stalled)")
+    p.add_argument("--no-served", action="store_true", help="skip the served sub-benchmark")
     p.add_argument("--no-build", action="store_true", help="skip the build-time sub-benchmark")
     p.add_argument("--no-e1", action="store_true", help="skip the 0%%-planted timing check")
     p.add_argument("--slots", type=int, default=8, help="requests a server holds on the device at once")
-    p.add_argument("--serve-merged", action="store_true",
-                   help="served form: scan requests admitted together in shared launches (experimental)")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)
@@ -633,7 +626,7 @@ def main():
         torch.cuda.empty_cache()
         build = bench_build(args, torch, ac, stream)
     served = None
-    if args.served and not args.no_served:
+    if not args.no_served:
         torch.cuda.empty_cache()
         served = bench_served(args, torch, ac, stream)
 

@@ -370,11 +370,13 @@ int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint
 
 /* ------------------------------------------------------------------ serving
  * A request loop over resident automata with continuous batching: requests
- * are admitted while others are on the device, as slots (HIP streams) and a
- * device-memory budget allow, and their scans overlap on the GPU. Each
- * request is scanned in pieces with the DFA state carried on the device from
- * one piece to the next (the per-buffer search of the paper's Alg. 1), and
- * its match list equals what ac_scan reports for the same text alone.
+ * are admitted while others are on the device, as slots (one HIP stream
+ * each) and a device-memory budget allow, and their scans overlap on the
+ * GPU. A request's work runs on its slot's stream alone. Automata the gated
+ * scan suits (AC_ALGO_AUTO's rule) scan a request in one gated launch; the
+ * others in pieces with the DFA state carried on the device from one piece to
+ * the next (the per-buffer search of the paper's Alg. 1). Either way a
+ * request's match list equals what ac_scan reports for the same text alone.
  */
 typedef struct ac_server ac_server;
 
@@ -386,17 +388,8 @@ typedef struct {
     uint32_t match_ppm;    /* first guess of matches per million text bytes, used to
                               size match lists until finished requests refine it;
                               0 = 20000. A low guess costs a rescan, never a result. */
-    uint32_t flags;        /* AC_SERVE_* bits */
+    uint32_t flags;        /* reserved, must be 0 */
 } ac_serve_opts;
-
-enum {
-    /* Experimental: requests of one kernel shape (LDS image or not,
-     * byte-class scheme) admitted together, each shorter than 64 MiB, are
-     * scanned in one shared launch and their keys handed out to the requests
-     * afterwards. By default every request scans on its own slot's stream,
-     * in pieces. */
-    AC_SERVE_MERGED = 2
-};
 
 typedef struct {
     int32_t status;           /* AC_OK or the error that ended the request */
@@ -408,7 +401,7 @@ typedef struct {
     uint64_t n_matches;
     uint64_t t_submit_ns, t_admit_ns, t_done_ns; /* arrival, admission and completion,
                                                     on the server's clock */
-    uint32_t pieces;          /* scan pieces */
+    uint32_t pieces;          /* scan launches of the last run (1 for a gated scan) */
     uint32_t rescans;         /* scans repeated because the list was too small */
 } ac_serve_result;
 
@@ -416,7 +409,6 @@ typedef struct {
     uint64_t submitted, completed, failed, queued, running, rescans;
     uint64_t pool_bytes, pool_used, pool_peak;
     uint64_t running_peak;  /* most requests on the device at once */
-    uint64_t merged_launches; /* shared launches issued */
     uint64_t bytes_done;    /* text bytes of successfully finished requests */
     double p50_ms, p99_ms;  /* latency (arrival to completion) of the last finished
                                requests, up to 65,536 of them; 0 if none */
@@ -443,9 +435,11 @@ int ac_serve_add(ac_server *s, const ac_automaton *a, uint32_t *id);
  * its arrival, so that a recorded or generated arrival process can be
  * replayed exactly: nothing is admitted before its arrival, and latency
  * counts from it (t_submit_ns). With text_on_device nonzero the
- * text is device memory (16-byte aligned) that must stay unchanged until the
+ * text is device memory (16-byte aligned), already written when the call is
+ * made (work queued on other streams to produce it must have completed: the
+ * server's streams do not wait on the caller's), and unchanged until the
  * request is done; otherwise it is host memory that the server copies into
- * its pool (use pinned memory for the copy to overlap other work), and that
+ * its pool (pinned memory copies without blocking the scheduler), and that
  * must stay valid until the request is done.
  * Errors: AC_ERR_INVALID; AC_ERR_TOO_LARGE if n >= 2^32 or the request alone
  * exceeds the budget.

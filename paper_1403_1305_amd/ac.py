@@ -38,7 +38,6 @@ AC_ALGO_GATED = 3
 AC_BUILD_GOTO_ONLY = 1
 AC_BUILD_PAIR_ROWS = 2
 AC_BUILD_NO_GATE = 4
-AC_SERVE_MERGED = 2
 AC_PAIR_AUTO, AC_PAIR_OFF = 0, 1
 
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
@@ -109,7 +108,7 @@ class ac_serve_result(ctypes.Structure):
 class ac_serve_stats_t(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "queued", "running",
                                                "rescans", "pool_bytes", "pool_used", "pool_peak",
-                                               "running_peak", "merged_launches", "bytes_done")] + \
+                                               "running_peak", "bytes_done")] + \
                [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("gbps", ctypes.c_double)]
 
 
@@ -365,6 +364,7 @@ class Server:
                  match_ppm: int = 0, flags: int = 0):
         lib = load_library()
         self.autos = list(autos)
+        self._texts = {}  # ticket -> the submitted text object, alive until release
         arr = (ctypes.c_void_p * len(self.autos))(*[a.handle for a in self.autos])
         o = ac_serve_opts(hbm_budget, max_inflight, piece_bytes, match_ppm, flags)
         h = _vp()
@@ -385,6 +385,7 @@ class Server:
         t = _u64()
         _check(load_library().ac_serve_submit(self.handle, automaton, _ptr(text), n, int(bool(on_device)),
                                               arrival_ns, ctypes.byref(t)))
+        self._texts[t.value] = text  # the server reads it until the request is done
         return t.value
 
     def add(self, automaton: Automaton) -> int:
@@ -422,6 +423,7 @@ class Server:
 
     def release(self, ticket: int) -> None:
         _check(load_library().ac_serve_release(self.handle, ticket))
+        self._texts.pop(ticket, None)
 
     def stats(self) -> dict:
         st = ac_serve_stats_t()
@@ -432,6 +434,7 @@ class Server:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.ac_serve_destroy(self.handle)
             self.handle = None
+            self._texts = {}
 
     __del__ = close
 

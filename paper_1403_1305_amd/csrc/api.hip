@@ -130,15 +130,6 @@ int build_common(const uint8_t *pat, const uint64_t *off, uint32_t n, const ac_b
     return AC_OK;
 }
 
-// The matcher AC_ALGO_AUTO runs: the gated failure-less scan where its gate
-// passes few enough start positions that walking them costs less than the
-// DFA's lookup per byte, else the DFA (the failure-less scan without DFA).
-constexpr double kGateAutoPass = 0.05;
-uint32_t auto_algo(const ac_automaton *a) {
-    if (a->dm.gate_bits && a->m.gate_pass <= kGateAutoPass) return AC_ALGO_GATED;
-    return a->m.goto_only ? AC_ALGO_PFAC : AC_ALGO_DFA;
-}
-
 bool resolve_placement(const ac_automaton *a, uint32_t want, uint32_t &place) {
     place = want == AC_PLACE_AUTO ? a->placement : want;
     if (place == AC_PLACE_LDS_HOT && a->m.hot_states == 0) return false;
@@ -298,7 +289,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         if (opts->pair_steps > AC_PAIR_OFF) return fail(AC_ERR_INVALID, "ac_scan: unknown pair_steps");
     }
     if (cfg.algo > AC_ALGO_GATED) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
-    if (cfg.algo == AC_ALGO_AUTO) cfg.algo = auto_algo(a);
+    if (cfg.algo == AC_ALGO_AUTO) cfg.algo = acm::auto_algo(a);
     if (cfg.algo == AC_ALGO_DFA && a->m.goto_only)
         return fail(AC_ERR_INVALID, "ac_scan: a goto-only automaton has no DFA (use AC_ALGO_PFAC or AC_ALGO_GATED)");
     if (cfg.algo == AC_ALGO_GATED && !a->dm.gate_bits)

@@ -641,83 +641,6 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(BatchArgs b) {
     em.flush();
 }
 
-// ------------------------------------------------------------------ served
-// Requests that a server scans together in one launch. A task covers
-// n_items chunks of one request (its own text pointer and automaton), at most
-// one per walker of a workgroup; item i owns end positions
-// [own_first + i * chunk, + chunk) of the request. Matches are keyed with the
-// request's slot above the position (position = slot << kSlotShift | end,
-// ends below 2^kSlotShift), so that one list serves the launch and a second
-// kernel hands every key to its request.
-constexpr uint32_t kSlotShift = 26;
-struct ServedTask {
-    const uint8_t *text;  // the request's text (16-byte aligned)
-    uint32_t own_first;   // first end position owned by item 0
-    uint32_t n_items;
-    uint32_t chunk;       // end positions per item (multiple of 16)
-    uint32_t text_len;    // the request's length, < 2^kSlotShift
-    uint32_t automaton;   // index into ServedArgs::autos
-    uint32_t slot;        // < 2^(32 - kSlotShift)
-};
-struct ServedArgs {
-    const ServedTask *tasks;
-    uint32_t n_tasks;
-    const DfaArgs *autos;
-    uint64_t *out;
-    uint64_t cap;
-    unsigned long long *count;
-    uint32_t *next_task;  // task counter, zero at launch
-};
-
-template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
-__global__ void __launch_bounds__(BLOCK) served_kernel(ServedArgs b) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    constexpr uint32_t kQueues = (BLOCK / 64) * kQueueBytesPerWave;
-    uint8_t *s_cmap = smem + kQueues;
-    uint32_t *s_tab = reinterpret_cast<uint32_t *>(smem + kQueues + 256);
-    uint16_t *s_hot = reinterpret_cast<uint16_t *>(smem + kQueues + 256);
-    const uint32_t tid = threadIdx.x;
-    __shared__ uint32_t s_task;
-    Emitter em;
-    em.init(smem, b.out, b.cap, b.count);
-    uint32_t loaded = 0xffffffffu;
-    while (true) {
-        // as in batch_kernel: tasks in increasing order from the counter
-        if (tid == 0) s_task = atomicAdd(b.next_task, 1u);
-        __syncthreads();
-        const uint32_t t = __builtin_amdgcn_readfirstlane(s_task);
-        __syncthreads();
-        if (t >= b.n_tasks) break;
-        const ServedTask task = b.tasks[t];
-        DfaArgs a = b.autos[task.automaton];
-        a.text = task.text;
-        a.out = b.out;
-        a.cap = b.cap;
-        a.count = b.count;
-        a.base = uint64_t(task.slot) << kSlotShift;
-        a.state_in = nullptr;
-        a.state_out = nullptr;
-        if (task.automaton != loaded) {
-            load_tables<PLACE, BLOCK>(a, s_cmap, s_tab, s_hot);
-            loaded = task.automaton;
-        }
-        const Walkers<PLACE, K, LOG2C, HASHED> W{a, s_cmap, s_tab, s_hot, em};
-        uint32_t s[K], own[K], hi[K], wstart[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t i = k * BLOCK + tid;
-            const bool act = i < task.n_items;
-            own[k] = act ? task.own_first + i * task.chunk : 0u;
-            hi[k] = act ? min(own[k] + task.chunk, task.text_len) : 0u;
-            // the walk never starts before the request's text
-            wstart[k] = (own[k] > a.back ? own[k] - a.back : 0u) & ~15u;
-            s[k] = 0;
-        }
-        walk_chunks<PLACE, K, LOG2C, HASHED, NBUF, G>(W, a, em, s_cmap, s_tab, s_hot, s, own, hi, wstart);
-    }
-    em.flush();
-}
-
 // Table pointers, sizes and class scheme of a machine (the text, output and
 // chunking fields are left for the caller).
 inline void fill_machine_args(const DeviceMachine &dm, DfaArgs &a) {
@@ -776,7 +699,6 @@ DfaKernel select_for(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes) 
 }
 
 using BatchKernel = void (*)(BatchArgs);
-using ServedKernel = void (*)(ServedArgs);
 
 // Batch kernel for a placement (LDS_HOT or GLOBAL), walker count, block size
 // and class scheme (shared by every automaton of the batch); ONLY_K as for
@@ -805,36 +727,8 @@ BatchKernel select_batch_for(bool hashed, int l2, uint32_t K, uint32_t block_byt
     return nullptr;
 }
 
-// Served kernel for a placement, walker count, block size and class scheme;
-// ONLY_K as for select_for.
-template <int PLACE, int ONLY_K = 0>
-ServedKernel select_served_for(bool hashed, int l2, uint32_t K, uint32_t block_bytes) {
-    constexpr bool kHot = PLACE == AC_PLACE_LDS_HOT;
-#define AC_S_V(KK, LL, HH, NB, GG)                                                                  \
-    return served_kernel<PLACE, KK, LL, HH, (kHot ? (KK == 4 ? 768 : 1024) : 256), NB, GG>;
-#define AC_S_CASE(KK, LL, HH)                                                                       \
-    if constexpr (ONLY_K == 0 || ONLY_K == KK) {                                                    \
-        if (K == KK && l2 == LL && hashed == HH) {                                                  \
-            if constexpr (KK >= 3) { AC_S_V(KK, LL, HH, 1, 4) }                                     \
-            else { AC_S_V(KK, LL, HH, 1, 8) }                                                       \
-        }                                                                                           \
-    }
-#define AC_S_KS(LL, HH) AC_S_CASE(1, LL, HH) AC_S_CASE(2, LL, HH) AC_S_CASE(3, LL, HH) AC_S_CASE(4, LL, HH)
-    AC_S_KS(-1, false)
-    AC_S_KS(0, true)
-    AC_S_KS(1, true)
-    AC_S_KS(2, true)
-    AC_S_KS(3, true)
-#undef AC_S_KS
-#undef AC_S_CASE
-#undef AC_S_V
-    return nullptr;
-}
-
 BatchKernel select_batch_hot(bool hashed, int l2, uint32_t K, uint32_t block_bytes);
 BatchKernel select_batch_global(bool hashed, int l2, uint32_t K, uint32_t block_bytes);
-ServedKernel select_served_hot(bool hashed, int l2, uint32_t K, uint32_t block_bytes);
-ServedKernel select_served_global(bool hashed, int l2, uint32_t K, uint32_t block_bytes);
 
 DfaKernel select_global(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);
 DfaKernel select_full(const DeviceMachine &dm, uint32_t K, uint32_t block_bytes);

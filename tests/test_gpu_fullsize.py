@@ -109,9 +109,15 @@ def test_full_served_configuration():
                for i in range(R)]
     sample = set(sample_indices(w.length, 16, 1 << 20))
     served_keys = {}
+    dfa = ac._scan_opts(ac.AC_ALGO_DFA)
     for i, t in enumerate(tickets):
         r = srv.wait(t, 60_000)  # fails the test instead of hanging it
         assert r.n_matches == plain_counts[i], i
+        # every request's whole list, sorted on the device, against a plain
+        # DFA scan of its text alone
+        got = torch.sort(srv.keys_tensor(r))[0]
+        plain = torch.sort(ac.scan_text(autos[int(w.automaton[i])], views[i], opts=dfa))[0]
+        assert torch.equal(got, plain), i
         if i in sample:
             served_keys[i] = np.sort(srv.keys(r))
         srv.release(t)

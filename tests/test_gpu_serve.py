@@ -94,33 +94,25 @@ def collect(srv, tickets):
     return out
 
 
-MODES = [0, ac.AC_SERVE_MERGED]  # one stream per request (default), shared launches
-
-
-# This case once left a request unfinished after the 60 s wait (the default
-# per-request mode, host and device texts mixed). No cause has been found in
-# the scheduler, so the case stays off until one is.
-STALLED = pytest.mark.skip(reason="a request once stayed unfinished past the bounded wait; cause not found")
-
-
-@pytest.mark.parametrize("flags", [pytest.param(0, marks=STALLED), ac.AC_SERVE_MERGED])
-def test_mix_equals_alone_and_oracle(setup, flags):
+def test_mix_equals_alone_and_oracle(setup):
+    """40 requests of mixed sizes, half from host memory, all arriving at one
+    time in 4 KiB pieces over 8 slots: every list equals the oracle's, and the
+    same request run alone gives the same list. (This case once stalled: a
+    request arriving between the scheduler's two clock readings of one pass
+    was left for a wake-up that never came; one reading per pass since.)"""
     sets, autos, reqs, expect = setup
-    srv = ac.Server(autos, hbm_budget=64 << 20, max_inflight=8, piece_bytes=PIECE, flags=flags)
+    srv = ac.Server(autos, hbm_budget=64 << 20, max_inflight=8, piece_bytes=PIECE)
     keep, tickets = submit_all(srv, reqs)
     mix = collect(srv, tickets)
     st = srv.stats()
     note("mix stats", st)
     assert st["completed"] == len(reqs) and st["failed"] == 0 and st["queued"] == 0
     assert st["running_peak"] > 1  # requests overlapped on the device
-    if flags & ac.AC_SERVE_MERGED:
-        assert 0 < st["merged_launches"] < len(reqs)  # requests shared launches
-    else:
-        assert st["merged_launches"] == 0
     for i, ((keys, pieces, _, r), e) in enumerate(zip(mix, expect)):
         assert np.array_equal(keys, e), i
-        per_request = (reqs[i][1].size + PIECE - 1) // PIECE
-        assert pieces == per_request or (flags and pieces == 1), (i, pieces)
+        gated = ac.ac_info(autos[reqs[i][0]])["gate_pass"] <= 0.05
+        per_request = 1 if gated else (reqs[i][1].size + PIECE - 1) // PIECE
+        assert pieces == per_request or reqs[i][1].size == 0, (i, pieces)
         assert r.t_submit_ns <= r.t_admit_ns <= r.t_done_ns
     # each request alone, on the same server
     for i, (a, text, on_dev) in enumerate(reqs):
@@ -144,13 +136,12 @@ def test_mix_equals_plain_scans(setup):
     srv.close()
 
 
-@pytest.mark.parametrize("flags", MODES)
-def test_small_budget_admits_by_memory(setup, flags):
+def test_small_budget_admits_by_memory(setup):
     """A budget that holds only a few requests at a time: admission waits for
     memory, every result is still exact, and the pool never exceeds it."""
     sets, autos, reqs, expect = setup
     budget = 1 << 20
-    srv = ac.Server(autos, hbm_budget=budget, max_inflight=16, piece_bytes=PIECE, flags=flags)
+    srv = ac.Server(autos, hbm_budget=budget, max_inflight=16, piece_bytes=PIECE)
     host_reqs = [(a, t, False) for a, t, _ in reqs]  # host texts take pool memory too
     keep, tickets = submit_all(srv, host_reqs)
     got = collect(srv, tickets)
@@ -163,15 +154,14 @@ def test_small_budget_admits_by_memory(setup, flags):
     srv.close()
 
 
-@pytest.mark.parametrize("flags", MODES)
-def test_low_match_estimate_rescans_exactly(setup, flags):
+def test_low_match_estimate_rescans_exactly(setup):
     """A match-rate guess far too low: requests overflow their lists and are
     scanned again into exact ones."""
     sets, autos, reqs, expect = setup
     # largest first, so the first requests admitted overflow before any
     # finished request can teach the server a better rate
     order = sorted(range(len(reqs)), key=lambda i: -reqs[i][1].size)
-    srv = ac.Server(autos, piece_bytes=PIECE, match_ppm=1, max_inflight=4, flags=flags)
+    srv = ac.Server(autos, piece_bytes=PIECE, match_ppm=1, max_inflight=4)
     keep, tickets = submit_all(srv, [reqs[i] for i in order])
     got = collect(srv, tickets)
     for g, i in zip(got, order):
