@@ -358,15 +358,38 @@ int ac_batch_scan(ac_batch *b, const uint8_t *d_texts, uint64_t *d_matches, uint
 void ac_batch_free(ac_batch *b);
 
 /*
- * ac_scan_batch -- one-shot form: plan, scan and free in one call, for texts
- * packed one after another. Text t is bytes [text_off[t], text_off[t+1]) of
- * d_texts (host array of n_texts + 1 offsets, each text start a multiple of
- * 16) and is matched against autos[text_auto[t]]. Keys and overflow as
- * ac_batch_scan. Synchronises `stream` before returning (the plan is freed).
+ * ac_scan_batch -- one-shot form, with the text descriptors in device memory:
+ * plan, scan and free in one call (Sec. III's input split, applied to many
+ * texts, each against its own machine, Sec. IV.A). Text t is bytes
+ * [d_text_off[t], d_text_off[t+1]) of the batch buffer d_texts and is matched
+ * against autos[d_text_auto[t]]. The work items are planned on the device
+ * (chunks of every text, ordered by automaton), so the descriptors never
+ * visit the host.
+ *
+ *   d_texts       device batch buffer, 16-byte aligned
+ *   d_text_off    device, n_texts + 1 non-decreasing uint64 offsets; each
+ *                 non-empty text starts at a multiple of 16; the last offset
+ *                 is below 2^32
+ *   d_text_auto   device, n_texts uint32 indices into autos
+ *   d_match_text  device, room for `capacity` uint32 (NULL = not wanted):
+ *                 receives, beside each key written to d_matches, the index
+ *                 of the text the match lies in
+ *   d_matches, capacity, d_count  keys as ac_batch_scan (end positions in
+ *                 the batch buffer); *d_count holds the true total
+ *   tune          NULL for defaults (placement, walkers, chunk)
+ *
+ * Device scratch for the plan (about 16 MB plus 4 bytes per text) is
+ * allocated and freed by the call. Synchronises `stream` before returning.
+ * Errors: AC_ERR_INVALID for NULL pointers, an unaligned buffer, automata
+ * that cannot share a launch, and (found by the device plan) decreasing
+ * offsets, unaligned text starts or an automaton index past n_autos;
+ * AC_ERR_TOO_LARGE for more than 2^19 texts or a buffer of 2^32 bytes or
+ * more; AC_ERR_NOMEM; AC_ERR_HIP.
  */
 int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint8_t *d_texts,
-                  const uint64_t *text_off, const uint32_t *text_auto, uint32_t n_texts, uint64_t *d_matches,
-                  uint64_t capacity, uint64_t *d_count, const ac_batch_tune *tune, void *stream);
+                  const uint64_t *d_text_off, const uint32_t *d_text_auto, uint32_t n_texts,
+                  uint32_t *d_match_text, uint64_t *d_matches, uint64_t capacity, uint64_t *d_count,
+                  const ac_batch_tune *tune, void *stream);
 
 /* ------------------------------------------------------------------ serving
  * A request loop over resident automata with continuous batching: requests

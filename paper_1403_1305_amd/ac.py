@@ -137,7 +137,7 @@ SIGNATURES = {
     "ac_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ac_batch_info_t)]),
     "ac_batch_scan": (ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, ctypes.c_int, _vp]),
     "ac_batch_free": (None, [_vp]),
-    "ac_scan_batch": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _u64, _vp,
+    "ac_scan_batch": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _u64, _vp,
                                      ctypes.POINTER(ac_batch_tune), _vp]),
     "ac_serve_create": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(ac_serve_opts), ctypes.POINTER(_vp)]),
     "ac_serve_add": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_u32)]),
@@ -439,17 +439,24 @@ class Server:
     __del__ = close
 
 
-def ac_scan_batch(autos, d_texts, text_off, text_auto, d_matches, capacity: int, d_count,
-                  tune: ac_batch_tune | None = None, stream=None) -> None:
-    """One-shot batch over texts packed back to back: text t is bytes
-    [text_off[t], text_off[t+1]) of d_texts (starts multiples of 16)."""
+def _scan_batch(fn: str, autos, d_texts, d_text_off, d_text_auto, d_matches, capacity: int, d_count,
+                d_match_text=None, tune: ac_batch_tune | None = None, stream=None) -> None:
     lib = load_library()
     arr = (ctypes.c_void_p * len(autos))(*[a.handle for a in autos])
-    off = np.ascontiguousarray(text_off, dtype=np.uint64)
-    au = np.ascontiguousarray(text_auto, dtype=np.uint32)
-    _check(lib.ac_scan_batch(arr, len(autos), _ptr(d_texts), off.ctypes.data, au.ctypes.data, len(off) - 1,
-                             _ptr(d_matches), capacity, _ptr(d_count),
-                             ctypes.byref(tune) if tune is not None else None, _stream(stream)))
+    n_texts = int(d_text_auto.numel()) if isinstance(d_text_auto, torch.Tensor) else len(d_text_auto)
+    _check(getattr(lib, fn)(arr, len(autos), _ptr(d_texts), _ptr(d_text_off), _ptr(d_text_auto), n_texts,
+                            _ptr(d_match_text), _ptr(d_matches), capacity, _ptr(d_count),
+                            ctypes.byref(tune) if tune is not None else None, _stream(stream)))
+
+
+def ac_scan_batch(autos, d_texts, d_text_off, d_text_auto, d_matches, capacity: int, d_count,
+                  d_match_text=None, tune: ac_batch_tune | None = None, stream=None) -> None:
+    """One-shot batch; the descriptors are device tensors: d_text_off (int64,
+    n_texts + 1, text t is bytes [off[t], off[t+1]) of d_texts) and
+    d_text_auto (int32, n_texts). d_match_text (int32, capacity) receives
+    each key's text index when given."""
+    _scan_batch("ac_scan_batch", autos, d_texts, d_text_off, d_text_auto, d_matches, capacity, d_count,
+                d_match_text, tune, stream)
 
 
 def pack_texts(texts, align: int = 16) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <memory>
+
 #include "automaton.h"
 #include "dfa_kernel.h"
 
@@ -103,6 +105,314 @@ int launch(ac_batch *b, const uint8_t *text, uint64_t *out, uint64_t cap, uint64
     args.next_task = b->d_next;
     const int rc = acm::launch_kernel(b->kernel, b->grid, b->block, b->lds, s, args, err);
     return rc == AC_OK ? AC_OK : set_error(rc, err);
+}
+
+// ------------------------------------------------------------ one-shot batches
+// ac_scan_batch takes the texts' offsets and automata in device memory, so
+// the work items are planned on the device, in a scratch buffer: a one-workgroup kernel validates the texts, picks the
+// chunk length from their total, counts each automaton's items and tasks and
+// gives every text its run of items (texts of one automaton in one block of
+// items); a kernel with a workgroup per text then writes its items; then the
+// persistent batch kernel runs the tasks, reading their count from the
+// scratch. The chunk is chosen so that the items never outnumber
+// kPlanMaxItems.
+
+// The scratch header (64 bytes).
+struct PlanHeader {
+    uint32_t n_tasks;    // tasks of the plan (0 when the texts were rejected)
+    uint32_t next_task;  // the persistent launch's task counter
+    uint32_t error;      // kPlan* code
+    uint32_t n_items;
+    uint32_t chunk;
+    uint32_t pad[11];
+};
+static_assert(sizeof(PlanHeader) == 64, "plan header");
+enum : uint32_t { kPlanOk = 0, kPlanBadOffsets = 1, kPlanMisaligned = 2, kPlanBadAutomaton = 3, kPlanTooLarge = 4 };
+
+constexpr uint32_t kPlanMaxItems = 1u << 20;
+constexpr uint32_t kPlanMaxTexts = kPlanMaxItems / 2;  // each text may end in a partial item
+constexpr uint32_t kBatchMaxAutos = 256;
+constexpr uint32_t kPlanThreads = 1024;
+
+// Byte offsets of the scratch parts for n_texts texts.
+struct PlanLayout {
+    size_t autos = 0, text_item = 0, tasks = 0, items = 0, bytes = 0;
+    uint32_t max_tasks = 0;
+};
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr PlanLayout plan_layout(uint32_t n_texts) {
+    PlanLayout l{};
+    l.autos = align256(sizeof(PlanHeader));
+    l.text_item = l.autos + align256(size_t(kBatchMaxAutos) * sizeof(acm::dfa::DfaArgs));
+    // a task holds at least 256 items (one per walker), each automaton ends one
+    l.max_tasks = kPlanMaxItems / 256 + kBatchMaxAutos + 1;
+    l.tasks = l.text_item + align256(size_t(n_texts) * 4);
+    l.items = l.tasks + align256(size_t(l.max_tasks) * sizeof(acm::dfa::BatchTask));
+    l.bytes = l.items + size_t(kPlanMaxItems) * sizeof(acm::dfa::BatchItem);
+    return l;
+}
+
+struct PlanParams {
+    const uint64_t *text_off;   // n_texts + 1 offsets into the batch buffer
+    const uint32_t *text_auto;  // n_texts automaton indices
+    uint32_t n_texts, n_autos, m_max, block_bytes, per_task;
+    uint64_t walkers;           // walkers of the persistent launch (chunk choice)
+    uint32_t tune_chunk;        // 0 = chosen from the total
+    PlanHeader *hdr;
+    uint32_t *text_item;        // first item of each text
+    acm::dfa::BatchTask *tasks;
+    unsigned long long *count;  // the caller's match count, zeroed here
+};
+
+__global__ void __launch_bounds__(kPlanThreads) batch_plan_kernel(PlanParams p) {
+    __shared__ unsigned long long s_total;
+    __shared__ uint32_t s_err;
+    __shared__ uint32_t s_items[kBatchMaxAutos], s_cursor[kBatchMaxAutos];
+    __shared__ uint32_t s_task_base[kBatchMaxAutos + 1], s_item_base[kBatchMaxAutos + 1];
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        s_total = 0;
+        s_err = kPlanOk;
+        *p.count = 0;
+    }
+    for (uint32_t a = tid; a < kBatchMaxAutos; a += kPlanThreads) s_items[a] = 0;
+    __syncthreads();
+    // every text: non-decreasing offsets, 16-byte aligned starts, an automaton
+    // of the batch, a buffer below 2^32 bytes
+    unsigned long long local = 0;
+    uint32_t err = kPlanOk;
+    for (uint32_t t = tid; t < p.n_texts; t += kPlanThreads) {
+        const uint64_t lo = p.text_off[t], hi = p.text_off[t + 1];
+        if (hi < lo) {
+            err = kPlanBadOffsets;
+            continue;
+        }
+        if (hi > lo && (lo & 15u)) err = kPlanMisaligned;
+        if (p.text_auto[t] >= p.n_autos) err = kPlanBadAutomaton;
+        if (hi >= (1ull << 32)) err = kPlanTooLarge;
+        local += hi - lo;
+    }
+    atomicAdd(&s_total, local);
+    if (err) atomicMax(&s_err, err);
+    __syncthreads();
+    if (s_err) {
+        if (tid == 0) {
+            p.hdr->error = s_err;
+            p.hdr->n_tasks = 0;
+            p.hdr->n_items = 0;
+        }
+        return;
+    }
+    // chunk: about four walks per walker of the launch, at least 4 m_max, in
+    // whole text blocks, and few enough items for the scratch
+    const uint64_t total = s_total, bb = p.block_bytes;
+    uint64_t c = p.tune_chunk ? p.tune_chunk
+                              : max((total + p.walkers * 4 - 1) / (p.walkers * 4), 4ull * p.m_max);
+    c = max(bb, (c + bb - 1) / bb * bb);
+    const uint64_t room = kPlanMaxItems - p.n_texts;  // each text may end in a partial item
+    if (total / c > room) c = ((total + room - 1) / room + bb - 1) / bb * bb;
+    c = min<uint64_t>(c, 1u << 30);
+    for (uint32_t t = tid; t < p.n_texts; t += kPlanThreads) {
+        const uint64_t len = p.text_off[t + 1] - p.text_off[t];
+        atomicAdd(&s_items[p.text_auto[t]], uint32_t((len + c - 1) / c));
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t base = 0, tbase = 0;
+        for (uint32_t a = 0; a < p.n_autos; ++a) {
+            s_item_base[a] = base;
+            s_cursor[a] = base;
+            s_task_base[a] = tbase;
+            base += s_items[a];
+            tbase += (s_items[a] + p.per_task - 1) / p.per_task;
+        }
+        s_item_base[p.n_autos] = base;
+        s_task_base[p.n_autos] = tbase;
+        p.hdr->n_items = base;
+        p.hdr->n_tasks = tbase;
+        p.hdr->chunk = uint32_t(c);
+        p.hdr->next_task = 0;
+        p.hdr->error = kPlanOk;
+    }
+    __syncthreads();
+    // tasks: runs of at most per_task items of one automaton
+    for (uint32_t k = tid; k < s_task_base[p.n_autos]; k += kPlanThreads) {
+        uint32_t a = 0;
+        while (s_task_base[a + 1] <= k) ++a;
+        const uint32_t b = s_item_base[a] + (k - s_task_base[a]) * p.per_task;
+        p.tasks[k] = acm::dfa::BatchTask{b, min(b + p.per_task, s_item_base[a + 1]), a, 0u};
+    }
+    // each text's run of items within its automaton's block (any order)
+    for (uint32_t t = tid; t < p.n_texts; t += kPlanThreads) {
+        const uint64_t len = p.text_off[t + 1] - p.text_off[t];
+        p.text_item[t] = atomicAdd(&s_cursor[p.text_auto[t]], uint32_t((len + c - 1) / c));
+    }
+}
+
+// The items of text blockIdx.x.
+__global__ void __launch_bounds__(256) batch_fill_kernel(const uint64_t *text_off, const PlanHeader *hdr,
+                                                         const uint32_t *text_item, acm::dfa::BatchItem *items) {
+    if (hdr->error) return;
+    const uint32_t t = blockIdx.x;
+    const uint64_t lo = text_off[t], hi = text_off[t + 1], c = hdr->chunk;
+    const uint32_t first = text_item[t], n = uint32_t((hi - lo + c - 1) / c);
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const uint64_t b = lo + uint64_t(j) * c;
+        items[first + j] = acm::dfa::BatchItem{uint32_t(b), uint32_t(min(hi, b + c)), uint32_t(lo), t};
+    }
+}
+
+// The text of each match: the last text whose offset is at or before the
+// match's end position.
+__global__ void match_text_kernel(const uint64_t *keys, const unsigned long long *count, uint64_t cap,
+                                  const uint64_t *text_off, uint32_t n_texts, uint32_t *match_text) {
+    const uint64_t n = min(uint64_t(*count), cap);
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t pos = keys[i] >> 32;
+        uint32_t lo = 0, hi = n_texts;  // largest t with text_off[t] <= pos lies in [lo, hi)
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (text_off[mid] <= pos)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        match_text[i] = lo;
+    }
+}
+
+// Everything of a one-shot batch that does not depend on the texts: the
+// kernel, its shape and the automata's arguments (host side).
+struct OneShot {
+    acm::dfa::BatchKernel kernel = nullptr;
+    uint32_t block = 0, lds = 0, grid = 0, walkers_per_lane = 1, bb = 128, m_max = 1;
+    acm::dfa::DfaArgs args[kBatchMaxAutos];
+};
+
+int prepare_one_shot(const char *fn, const ac_automaton *const *autos, uint32_t n_autos,
+                     const ac_batch_tune *tune, OneShot &o) {
+    auto f = [fn] { return std::string(fn); };  // built only for an error message
+    if (!autos || n_autos == 0 || n_autos > kBatchMaxAutos)
+        return set_error(AC_ERR_INVALID, f() + ": need 1 to 256 automata");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(AC_ERR_HIP, f() + ": hipGetDevice failed");
+    bool all_images = true;
+    for (uint32_t i = 0; i < n_autos; ++i) {
+        const ac_automaton *a = autos[i];
+        if (!a || !a->on_device || a->device != dev || a->m.goto_only)
+            return set_error(AC_ERR_INVALID, f() + ": automaton " + std::to_string(i) +
+                                                 " is NULL, host-only, goto-only or on another device");
+        if (a->m.hashed != autos[0]->m.hashed || (a->m.hashed && a->m.log2_cols != autos[0]->m.log2_cols))
+            return set_error(AC_ERR_INVALID, f() + ": automata must share one byte-class scheme");
+        all_images &= a->m.hot_states > 0;
+        o.m_max = std::max(o.m_max, a->m.m_max);
+        o.args[i] = acm::dfa::DfaArgs{};
+        acm::dfa::fill_machine_args(a->dm, o.args[i]);
+    }
+    const uint32_t want = tune ? tune->placement : AC_PLACE_AUTO;
+    const uint32_t place = want == AC_PLACE_AUTO ? (all_images ? AC_PLACE_LDS_HOT : AC_PLACE_GLOBAL) : want;
+    if ((place != AC_PLACE_LDS_HOT && place != AC_PLACE_GLOBAL) || (place == AC_PLACE_LDS_HOT && !all_images))
+        return set_error(AC_ERR_INVALID, f() + ": placement must be AUTO, GLOBAL, or LDS_HOT with an image in every automaton");
+    const uint32_t K = tune && tune->walkers ? tune->walkers : (place == AC_PLACE_LDS_HOT ? 2u : 1u);
+    if (K < 1 || K > 4) return set_error(AC_ERR_INVALID, f() + ": walkers must be 1, 2, 3 or 4");
+    if (tune && tune->chunk % 16) return set_error(AC_ERR_INVALID, f() + ": chunk must be a multiple of 16");
+    o.walkers_per_lane = K;
+    o.bb = K >= 3 ? 64u : 128u;
+    const bool hashed = autos[0]->m.hashed;
+    const int l2 = hashed ? int(autos[0]->m.log2_cols) : -1;
+    o.kernel = place == AC_PLACE_LDS_HOT ? acm::dfa::select_batch_hot(hashed, l2, K, o.bb)
+                                         : acm::dfa::select_batch_global(hashed, l2, K, o.bb);
+    if (!o.kernel) return set_error(AC_ERR_INVALID, f() + ": no batch kernel for this class scheme");
+    o.block = place == AC_PLACE_LDS_HOT ? (K == 4 ? 768u : 1024u) : 256u;
+    uint32_t image = 0;
+    if (place == AC_PLACE_LDS_HOT)
+        for (uint32_t i = 0; i < n_autos; ++i)
+            image = std::max<uint32_t>(image, ((autos[i]->m.hot_states * autos[i]->m.n_cols * 2u) + 15u) & ~15u);
+    o.lds = (o.block / 64) * acm::kQueueBytesPerWave + 256 + image;
+    if (o.lds > acm::kLdsPerWorkgroup) return set_error(AC_ERR_INVALID, f() + ": an LDS image does not fit");
+    if (acm::allow_lds(reinterpret_cast<const void *>(o.kernel), o.lds) != hipSuccess)
+        return set_error(AC_ERR_HIP, f() + ": hipFuncSetAttribute failed");
+    const int occ = acm::occupancy(reinterpret_cast<const void *>(o.kernel), o.block, o.lds);
+    o.grid = uint32_t(std::max<int64_t>(1, int64_t(acm::compute_units(dev)) * occ));
+    return AC_OK;
+}
+
+// Plan and scan a one-shot batch in `scratch` (at least plan_layout(n_texts)
+// bytes of device memory), then wait for `stream` and report a rejected plan.
+int run_one_shot(const char *fn, const OneShot &o, uint32_t n_autos, const uint8_t *d_texts, const uint64_t *d_text_off,
+                 const uint32_t *d_text_auto, uint32_t n_texts, uint32_t *d_match_text, uint64_t *d_matches,
+                 uint64_t capacity, uint64_t *d_count, const ac_batch_tune *tune, uint8_t *scratch, hipStream_t s) {
+    auto f = [fn] { return std::string(fn); };  // built only for an error message
+    const PlanLayout L = plan_layout(n_texts);
+    PlanHeader *hdr = reinterpret_cast<PlanHeader *>(scratch);
+    auto *d_autos = reinterpret_cast<acm::dfa::DfaArgs *>(scratch + L.autos);
+    hipError_t e = hipMemcpyAsync(d_autos, o.args, size_t(n_autos) * sizeof(acm::dfa::DfaArgs), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return set_error(AC_ERR_HIP, f() + ": " + hipGetErrorString(e));
+    PlanParams pp{};
+    pp.text_off = d_text_off;
+    pp.text_auto = d_text_auto;
+    pp.n_texts = n_texts;
+    pp.n_autos = n_autos;
+    pp.m_max = o.m_max;
+    pp.block_bytes = o.bb;
+    pp.per_task = o.block * o.walkers_per_lane;
+    pp.walkers = uint64_t(o.grid) * o.block * o.walkers_per_lane;
+    pp.tune_chunk = tune ? tune->chunk : 0u;
+    pp.hdr = hdr;
+    pp.text_item = reinterpret_cast<uint32_t *>(scratch + L.text_item);
+    pp.tasks = reinterpret_cast<acm::dfa::BatchTask *>(scratch + L.tasks);
+    pp.count = reinterpret_cast<unsigned long long *>(d_count);
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, pp);
+    auto *items = reinterpret_cast<acm::dfa::BatchItem *>(scratch + L.items);
+    if (n_texts) hipLaunchKernelGGL(batch_fill_kernel, dim3(n_texts), dim3(256), 0, s, d_text_off, hdr, pp.text_item, items);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(AC_ERR_HIP, f() + ": plan launch: " + hipGetErrorString(e));
+    acm::dfa::BatchArgs args{};
+    args.text = d_texts;
+    args.items = items;
+    args.tasks = pp.tasks;
+    args.n_tasks = 0;
+    args.n_tasks_dev = &hdr->n_tasks;
+    args.autos = d_autos;
+    args.out = d_matches;
+    args.cap = capacity;
+    args.count = reinterpret_cast<unsigned long long *>(d_count);
+    args.next_task = &hdr->next_task;
+    hipError_t le = acm::allow_lds(reinterpret_cast<const void *>(o.kernel), o.lds);
+    if (le == hipSuccess) {
+        hipLaunchKernelGGL(o.kernel, dim3(o.grid), dim3(o.block), o.lds, s, args);
+        le = hipGetLastError();
+    }
+    if (le != hipSuccess) return set_error(AC_ERR_HIP, f() + ": batch launch: " + hipGetErrorString(le));
+    if (d_match_text && capacity) {
+        hipLaunchKernelGGL(match_text_kernel, dim3(1024), dim3(256), 0, s, d_matches,
+                           reinterpret_cast<const unsigned long long *>(d_count), capacity, d_text_off, n_texts,
+                           d_match_text);
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_error(AC_ERR_HIP, f() + ": match text launch: " + hipGetErrorString(e));
+    }
+    PlanHeader h{};
+    e = hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(AC_ERR_HIP, f() + ": " + hipGetErrorString(e));
+    switch (h.error) {
+        case kPlanOk: return AC_OK;
+        case kPlanBadOffsets: return set_error(AC_ERR_INVALID, f() + ": decreasing text offsets");
+        case kPlanMisaligned: return set_error(AC_ERR_INVALID, f() + ": text starts must be multiples of 16");
+        case kPlanBadAutomaton: return set_error(AC_ERR_INVALID, f() + ": a text names an automaton past n_autos");
+        default: return set_error(AC_ERR_TOO_LARGE, f() + ": the batch buffer must stay below 2^32 bytes");
+    }
+}
+
+int check_one_shot_args(const char *fn, const uint8_t *d_texts, const uint64_t *d_text_off,
+                        const uint32_t *d_text_auto, uint32_t n_texts, uint64_t *d_matches, uint64_t capacity,
+                        uint64_t *d_count) {
+    auto f = [fn] { return std::string(fn); };  // built only for an error message
+    if (!d_count || !d_text_off) return set_error(AC_ERR_INVALID, f() + ": NULL count or text offsets");
+    if (n_texts && (!d_texts || !d_text_auto)) return set_error(AC_ERR_INVALID, f() + ": NULL texts or automaton indices");
+    if (capacity && !d_matches) return set_error(AC_ERR_INVALID, f() + ": NULL match buffer");
+    if (reinterpret_cast<uintptr_t>(d_texts) & 15u) return set_error(AC_ERR_INVALID, f() + ": the batch buffer must be 16-byte aligned");
+    return AC_OK;
 }
 
 }  // namespace
@@ -330,30 +640,26 @@ void ac_batch_free(ac_batch *b) {
 }
 
 int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint8_t *d_texts,
-                  const uint64_t *text_off, const uint32_t *text_auto, uint32_t n_texts, uint64_t *d_matches,
-                  uint64_t capacity, uint64_t *d_count, const ac_batch_tune *tune, void *stream) {
-    if (n_texts > 0 && !text_off) return set_error(AC_ERR_INVALID, "ac_scan_batch: NULL text offsets");
-    std::vector<uint64_t> off, len;
-    try {
-        off.resize(n_texts);
-        len.resize(n_texts);
-    } catch (const std::bad_alloc &) {
-        return set_error(AC_ERR_NOMEM, "ac_scan_batch: out of host memory");
-    }
-    for (uint32_t t = 0; t < n_texts; ++t) {
-        if (text_off[t + 1] < text_off[t]) return set_error(AC_ERR_INVALID, "ac_scan_batch: decreasing text offsets");
-        off[t] = text_off[t];
-        len[t] = text_off[t + 1] - text_off[t];
-    }
-    ac_batch *b = nullptr;
-    int rc = ac_batch_create(autos, n_autos, off.data(), len.data(), text_auto, n_texts, tune, stream, &b);
+                  const uint64_t *d_text_off, const uint32_t *d_text_auto, uint32_t n_texts, uint32_t *d_match_text,
+                  uint64_t *d_matches, uint64_t capacity, uint64_t *d_count, const ac_batch_tune *tune, void *stream) {
+    static const char *fn = "ac_scan_batch";
+    int rc = check_one_shot_args(fn, d_texts, d_text_off, d_text_auto, n_texts, d_matches, capacity, d_count);
     if (rc != AC_OK) return rc;
-    rc = ac_batch_scan(b, d_texts, d_matches, capacity, d_count, 0, stream);
-    // the plan's device arrays must outlive the launch
-    const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-    ac_batch_free(b);
-    if (rc != AC_OK) return rc;
-    return e == hipSuccess ? AC_OK : set_error(AC_ERR_HIP, std::string("ac_scan_batch: ") + hipGetErrorString(e));
+    if (n_texts > kPlanMaxTexts)
+        return set_error(AC_ERR_TOO_LARGE, "ac_scan_batch: at most 2^19 texts (the plan holds 2^20 work items)");
+    std::unique_ptr<OneShot> o(new (std::nothrow) OneShot());
+    if (!o) return set_error(AC_ERR_NOMEM, "ac_scan_batch: out of host memory");
+    if ((rc = prepare_one_shot(fn, autos, n_autos, tune, *o)) != AC_OK) return rc;
+    void *scr = nullptr;
+    hipError_t e = hipMalloc(&scr, plan_layout(n_texts).bytes);
+    if (e != hipSuccess) return set_error(AC_ERR_NOMEM, std::string("ac_scan_batch: scratch: ") + hipGetErrorString(e));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = run_one_shot(fn, *o, n_autos, d_texts, d_text_off, d_text_auto, n_texts, d_match_text, d_matches, capacity,
+                      d_count, tune, static_cast<uint8_t *>(scr), s);
+    // the plan in the scratch must outlive the launches
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(scr);
+    return rc;
 }
 
 }  // extern "C"

@@ -586,6 +586,7 @@ struct BatchArgs {
     uint64_t cap;
     unsigned long long *count;
     uint32_t *next_task;   // task counter, zero at launch
+    const uint32_t *n_tasks_dev;  // if set, the task count is read here (a plan built on the device)
 };
 
 template <int PLACE, int K, int LOG2C, bool HASHED, int BLOCK, int NBUF, int G>
@@ -599,6 +600,7 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(BatchArgs b) {
     __shared__ uint32_t s_task;
     Emitter em;
     em.init(smem, b.out, b.cap, b.count);
+    const uint32_t n_tasks = b.n_tasks_dev ? __builtin_amdgcn_readfirstlane(*b.n_tasks_dev) : b.n_tasks;
     uint32_t loaded = 0xffffffffu;
     while (true) {
         // the first barrier also ends every thread's previous task, so the
@@ -609,7 +611,7 @@ __global__ void __launch_bounds__(BLOCK) batch_kernel(BatchArgs b) {
         // arguments in scalar registers
         const uint32_t t = __builtin_amdgcn_readfirstlane(s_task);
         __syncthreads();
-        if (t >= b.n_tasks) break;
+        if (t >= n_tasks) break;
         const BatchTask task = b.tasks[t];
         DfaArgs a = b.autos[task.automaton];
         a.text = b.text;

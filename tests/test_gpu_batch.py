@@ -218,20 +218,59 @@ def test_batch_rejects_bad_plans():
         ac.ac_batch_scan(b, d[1:], out, 16, cnt)
 
 
-def test_one_shot_scan_batch(dna_batch):
-    """ac_scan_batch over texts packed back to back (CSR offsets) equals the
-    oracle, text by text."""
-    texts, sets, text_set, autos, _ = dna_batch
-    # pad each text to a multiple of 16 with a byte outside every pattern, so
-    # the packed texts are back to back and every start stays aligned
+def packed(texts):
+    """Each text padded to a multiple of 16 with a byte outside every pattern,
+    so that the texts lie back to back with aligned starts."""
     padded = [np.concatenate([t, np.full((-t.size) % 16, ord("N"), np.uint8)]) for t in texts]
     off = np.concatenate([[0], np.cumsum([p.size for p in padded])]).astype(np.uint64)
     buf = np.concatenate(padded) if padded else np.zeros(16, np.uint8)
-    expect = expected(padded, sets, text_set, off[:-1])
+    return padded, off, buf
+
+
+def one_shot(fn, autos, buf, off, text_set, cap, with_text=True):
     d = torch.from_numpy(buf).to("cuda")
-    cap = max(4096, 2 * buf.size)
-    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    d_off = torch.from_numpy(off.astype(np.int64)).to("cuda")
+    d_auto = torch.from_numpy(np.asarray(text_set, dtype=np.int32)).to("cuda")
+    out = torch.empty(max(1, cap), dtype=torch.int64, device="cuda")
+    mt = torch.full((max(1, cap),), -1, dtype=torch.int32, device="cuda") if with_text else None
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ac.ac_scan_batch(autos, d, off, text_set, out, cap, cnt)
+    fn(autos, d, d_off, d_auto, out, cap, cnt, d_match_text=mt)
     n = int(cnt.item())
-    assert np.array_equal(np.sort(ac.keys_to_numpy(out[:n])), expect)
+    keys = ac.keys_to_numpy(out[:min(n, cap)])
+    texts = mt[:min(n, cap)].cpu().numpy() if with_text else None
+    return n, keys, texts
+
+
+def test_one_shot_scan_batch(dna_batch):
+    """ac_scan_batch over texts packed back to back, descriptors on the
+    device, equals the oracle text by text; each key's text index is the text
+    its end position lies in."""
+    texts, sets, text_set, autos, _ = dna_batch
+    padded, off, buf = packed(texts)
+    expect = expected(padded, sets, text_set, off[:-1])
+    cap = max(4096, 2 * buf.size)
+    n, keys, mt = one_shot(ac.ac_scan_batch, autos, buf, off, text_set, cap)
+    assert n == expect.size
+    assert np.array_equal(np.sort(keys), expect)
+    pos = (keys >> np.uint64(32)).astype(np.int64)
+    t = np.searchsorted(off.astype(np.int64), pos, side="right") - 1
+    assert np.array_equal(mt, t.astype(np.int32))
+
+
+def test_one_shot_rejects_bad_descriptors(dna_batch):
+    texts, sets, text_set, autos, _ = dna_batch
+    padded, off, buf = packed(texts[:6])
+    ts = np.asarray(text_set[:6], dtype=np.int32)
+    bad_auto = ts.copy()
+    bad_auto[2] = len(autos)
+    with pytest.raises(ac.AcError) as e:
+        one_shot(ac.ac_scan_batch, autos, buf, off, bad_auto, 1024)
+    assert e.value.status == ac.AC_ERR_INVALID
+    bad_off = off.copy()
+    bad_off[3] = bad_off[3] + 1  # an unaligned start
+    with pytest.raises(ac.AcError) as e:
+        one_shot(ac.ac_scan_batch, autos, buf, bad_off, ts, 1024)
+    assert e.value.status == ac.AC_ERR_INVALID
+    # the same call with valid descriptors still works afterwards
+    n, keys, _ = one_shot(ac.ac_scan_batch, autos, buf, off, ts, 1 << 16)
+    assert np.array_equal(np.sort(keys), expected(padded, sets, ts, off[:-1]))
