@@ -378,7 +378,7 @@ void ac_batch_free(ac_batch *b);
  *                 the batch buffer); *d_count holds the true total
  *   tune          NULL for defaults (placement, walkers, chunk)
  *
- * Device scratch for the plan (about 16 MB plus 4 bytes per text) is
+ * Device scratch for the plan (about 17 MB plus 4 bytes per text) is
  * allocated and freed by the call. Synchronises `stream` before returning.
  * Errors: AC_ERR_INVALID for NULL pointers, an unaligned buffer, automata
  * that cannot share a launch, and (found by the device plan) decreasing
@@ -390,6 +390,27 @@ int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint
                   const uint64_t *d_text_off, const uint32_t *d_text_auto, uint32_t n_texts,
                   uint32_t *d_match_text, uint64_t *d_matches, uint64_t capacity, uint64_t *d_count,
                   const ac_batch_tune *tune, void *stream);
+
+/*
+ * ac_scan_batch_noalloc -- ac_scan_batch for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, harnesses
+ * that forbid allocation): the same arguments and results, with the plan in
+ * a scratch array of fixed size inside the library (one per GPU, held until
+ * the process ends) instead of a buffer allocated per call. It calls no
+ * hipMalloc or hipFree.
+ *
+ * Limits: at most 65,536 texts (AC_ERR_TOO_LARGE beyond); the scratch holds
+ * up to 2^20 work items, and the chunk length grows to stay within that.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (on different streams, or from threads that do not wait for each
+ * other) race on it and must not be made; calls from several host threads
+ * take turns on the host side. Synchronises `stream` before returning.
+ * Errors as ac_scan_batch, minus AC_ERR_NOMEM.
+ */
+int ac_scan_batch_noalloc(const ac_automaton *const *autos, uint32_t n_autos, const uint8_t *d_texts,
+                          const uint64_t *d_text_off, const uint32_t *d_text_auto, uint32_t n_texts,
+                          uint32_t *d_match_text, uint64_t *d_matches, uint64_t capacity, uint64_t *d_count,
+                          const ac_batch_tune *tune, void *stream);
 
 /* ------------------------------------------------------------------ serving
  * A request loop over resident automata with continuous batching: requests

@@ -139,6 +139,8 @@ SIGNATURES = {
     "ac_batch_free": (None, [_vp]),
     "ac_scan_batch": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _u64, _vp,
                                      ctypes.POINTER(ac_batch_tune), _vp]),
+    "ac_scan_batch_noalloc": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp, _u64, _vp,
+                                             ctypes.POINTER(ac_batch_tune), _vp]),
     "ac_serve_create": (ctypes.c_int, [_vp, _u32, ctypes.POINTER(ac_serve_opts), ctypes.POINTER(_vp)]),
     "ac_serve_add": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_u32)]),
     "ac_serve_submit": (ctypes.c_int, [_vp, _u32, _vp, _u64, ctypes.c_int, _u64, ctypes.POINTER(_u64)]),
@@ -456,6 +458,14 @@ def ac_scan_batch(autos, d_texts, d_text_off, d_text_auto, d_matches, capacity: 
     d_text_auto (int32, n_texts). d_match_text (int32, capacity) receives
     each key's text index when given."""
     _scan_batch("ac_scan_batch", autos, d_texts, d_text_off, d_text_auto, d_matches, capacity, d_count,
+                d_match_text, tune, stream)
+
+
+def ac_scan_batch_noalloc(autos, d_texts, d_text_off, d_text_auto, d_matches, capacity: int, d_count,
+                          d_match_text=None, tune: ac_batch_tune | None = None, stream=None) -> None:
+    """ac_scan_batch with the plan in the library's fixed scratch array (no
+    device allocation; at most 65,536 texts; calls on one GPU must not overlap)."""
+    _scan_batch("ac_scan_batch_noalloc", autos, d_texts, d_text_off, d_text_auto, d_matches, capacity, d_count,
                 d_match_text, tune, stream)
 
 

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include <memory>
+#include <mutex>
 
 #include "automaton.h"
 #include "dfa_kernel.h"
@@ -108,8 +109,9 @@ int launch(ac_batch *b, const uint8_t *text, uint64_t *out, uint64_t cap, uint64
 }
 
 // ------------------------------------------------------------ one-shot batches
-// ac_scan_batch takes the texts' offsets and automata in device memory, so
-// the work items are planned on the device, in a scratch buffer: a one-workgroup kernel validates the texts, picks the
+// ac_scan_batch and ac_scan_batch_noalloc take the texts' offsets and
+// automata in device memory, so the work items are planned on the device, in
+// a scratch buffer: a one-workgroup kernel validates the texts, picks the
 // chunk length from their total, counts each automaton's items and tasks and
 // gives every text its run of items (texts of one automaton in one block of
 // items); a kernel with a workgroup per text then writes its items; then the
@@ -415,6 +417,31 @@ int check_one_shot_args(const char *fn, const uint8_t *d_texts, const uint64_t *
     return AC_OK;
 }
 
+// The no-allocation form's scratch: one array per GPU, for up to
+// kNoAllocMaxTexts texts. Host code reaches it only through the address that
+// hipGetSymbolAddress gives on each device.
+constexpr uint32_t kNoAllocMaxTexts = 1u << 16;
+constexpr size_t kNoAllocScratchBytes = plan_layout(kNoAllocMaxTexts).bytes;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[64] = {};
+
+// This device's copy of `scratch` (looked up once per device, current).
+int scratch_address(int dev, uint8_t **out) {
+    if (dev < 0 || dev >= 64) return set_error(AC_ERR_INVALID, "ac_scan_batch_noalloc: device index past 63");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(AC_ERR_HIP, std::string("ac_scan_batch_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return AC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -660,6 +687,29 @@ int ac_scan_batch(const ac_automaton *const *autos, uint32_t n_autos, const uint
     (void)hipStreamSynchronize(s);
     (void)hipFree(scr);
     return rc;
+}
+
+int ac_scan_batch_noalloc(const ac_automaton *const *autos, uint32_t n_autos, const uint8_t *d_texts,
+                          const uint64_t *d_text_off, const uint32_t *d_text_auto, uint32_t n_texts,
+                          uint32_t *d_match_text, uint64_t *d_matches, uint64_t capacity, uint64_t *d_count,
+                          const ac_batch_tune *tune, void *stream) {
+    static const char *fn = "ac_scan_batch_noalloc";
+    int rc = check_one_shot_args(fn, d_texts, d_text_off, d_text_auto, n_texts, d_matches, capacity, d_count);
+    if (rc != AC_OK) return rc;
+    if (n_texts > kNoAllocMaxTexts)
+        return set_error(AC_ERR_TOO_LARGE, "ac_scan_batch_noalloc: at most 65536 texts (its scratch array is fixed)");
+    // the host-side plan in static storage (no allocation); calls that
+    // overlap on one GPU race on the scratch anyway, so they take turns here
+    static OneShot o;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    if ((rc = prepare_one_shot(fn, autos, n_autos, tune, o)) != AC_OK) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(AC_ERR_HIP, "ac_scan_batch_noalloc: hipGetDevice failed");
+    uint8_t *scr = nullptr;
+    if ((rc = scratch_address(dev, &scr)) != AC_OK) return rc;
+    return run_one_shot(fn, o, n_autos, d_texts, d_text_off, d_text_auto, n_texts, d_match_text, d_matches, capacity,
+                        d_count, tune, scr, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
