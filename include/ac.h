@@ -52,18 +52,22 @@ enum {
 /* Which device matcher a scan runs. Every one reports the same matches. */
 enum {
     AC_ALGO_AUTO = 0,  /* GATED when the automaton has a start-position gate that
-                          passes at most 1 window code in 20, else DFA (PFAC for
-                          a goto-only automaton) */
+                          is expected to pass at most 1 start position in 20,
+                          else DFA (PFAC for a goto-only automaton) */
     AC_ALGO_DFA = 1,   /* failure transitions folded into a full DFA, walked over
                           overlapping chunks of the text */
     AC_ALGO_PFAC = 2,  /* failure-less machine, one walk per start position */
     AC_ALGO_GATED = 3  /* failure-less machine, walked only from the start
-                          positions whose next 10 bytes can begin a pattern:
-                          a bitmap over the 4^10 class strings of 10 bytes,
-                          held in LDS, decides, and a table over them takes
-                          the walk's first 10 steps at once (automata whose
-                          patterns use at most four letters told apart by a
-                          2-bit field of the byte; ac_info_t.gate_pass) */
+                          positions whose next bytes can begin a pattern, as
+                          a bitmap held in LDS decides. The class gate (patterns
+                          over at most four letters told apart by a 2-bit field
+                          of the byte) covers the 4^10 class strings of 10
+                          bytes, and a table over them takes the walk's first
+                          10 steps at once. The hashed gate (every pattern 6
+                          bytes or longer) is a blocked Bloom filter over the
+                          patterns' first 6 bytes, and a hash table of those
+                          windows takes the first 6 steps (ac_info_t.has_gate,
+                          gate_pass) */
 };
 
 typedef struct ac_automaton ac_automaton;
@@ -114,10 +118,14 @@ typedef struct {
     uint32_t goto_only;    /* 1 if built with AC_BUILD_GOTO_ONLY */
     uint32_t pair_states;  /* states outside the LDS_HOT image with two-byte rows
                               (built with AC_BUILD_PAIR_ROWS); 0 if none */
-    uint32_t has_gate;     /* 1 if the start-position gate of AC_ALGO_GATED was built */
-    double gate_pass;      /* fraction of the 4^10 window class strings that the gate
-                              passes (1.0 without a gate): the share of start
-                              positions of uniformly random text that are walked */
+    uint32_t has_gate;     /* start-position gate of AC_ALGO_GATED: 0 none, 1 the
+                              class gate, 2 the hashed gate */
+    double gate_pass;      /* expected share of start positions the gate passes (1.0
+                              without a gate). Class gate: the fraction of the 4^10
+                              window class strings it passes (uniformly random
+                              text). Hashed gate: the chance that 6 bytes drawn with
+                              the patterns' byte frequencies begin a pattern, plus
+                              the filter's false-positive rate */
 } ac_info_t;
 
 /*
@@ -174,10 +182,22 @@ enum {
     AC_TABLE_PATH_OFF = 12,  /* uint32 [n_states+1]: patterns ending on the path from
                                 the root to s (states of depth <= 10) ... */
     AC_TABLE_PATH_IDS = 13,  /* uint32: ... in PATH_IDS[off[s] .. off[s+1]), ascending */
-    AC_TABLE_GATE2_BITS = 14 /* uint32 [2^11]: second gate level, bit h set for
+    AC_TABLE_GATE2_BITS = 14, /* uint32 [2^11]: second gate level, bit h set for
                                 h = (y * 0x9E3779B1) >> 16 (32-bit product) of every
                                 class string y of 12 bytes (first byte in the lowest
                                 2 bits) that a pattern can begin with */
+    AC_TABLE_QGATE_BITS = 15, /* uint32 [2^15]: hashed gate. For the first 6 bytes
+                                b0..b5 of every pattern, X = b0 | b1 << 8 | b2 << 16,
+                                Y = b3 | b4 << 8 | b5 << 16 and
+                                h = X * 0x9E3779 ^ Y * 0x85EBCB (32-bit products),
+                                word h >> 17 has bits (h >> 12) & 31 and
+                                (h >> 7) & 31 set (empty without this gate) */
+    AC_TABLE_QGATE_TAB = 16   /* uint32 [slots][4], slots a power of two: one entry
+                                per distinct 6-byte pattern start,
+                                {X | (Y & 255) << 24, Y >> 8 | 1 << 31, goto state
+                                after the 6 bytes, 1 if patterns end there}, at the
+                                first free slot from
+                                (X * 0xC2B2AF ^ Y * 0x27D4EB) >> (32 - log2 slots) on */
 };
 
 /*
@@ -512,6 +532,26 @@ int ac_serve_stats(ac_server *s, ac_serve_stats_t *st);
  * queued with AC_ERR_BUSY, stop the thread and free everything (unreleased
  * match lists included). NULL is a no-op. */
 void ac_serve_destroy(ac_server *s);
+
+/* ------------------------------------------------------------- measurement
+ * Streaming kernels of known traffic that the scans are priced against. They
+ * match nothing.
+ *
+ * ac_hbm_read -- read the n bytes at device pointer d (16-byte aligned) once,
+ * with the scans' 16-byte non-temporal loads over the whole GPU, and
+ * XOR-accumulate them into *d_fold as 32-bit little-endian words (a short
+ * last word zero-padded): *d_fold ^= fold. The time of one call on a buffer
+ * far larger than the caches is the HBM read ceiling.
+ * ac_hbm_copy -- copy n bytes from src to dst (device, 16-byte aligned, not
+ * overlapping) with the same loads and non-temporal stores: a kernel that
+ * reads n and writes n bytes, for scaling HBM byte counters.
+ * `blocks` is the workgroup count (256 threads each); 0 picks one per
+ * compute unit. Both are asynchronous on `stream`.
+ * Errors: AC_ERR_INVALID for NULL or unaligned pointers, overlapping copies;
+ * AC_ERR_HIP for a failed launch.
+ */
+int ac_hbm_read(const void *d, uint64_t n, uint64_t *d_fold, uint32_t blocks, void *stream);
+int ac_hbm_copy(void *dst, const void *src, uint64_t n, uint32_t blocks, void *stream);
 
 /* ac_last_error -- message of the last failing call on this thread ("" if none). */
 const char *ac_last_error(void);

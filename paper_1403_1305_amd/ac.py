@@ -43,7 +43,7 @@ AC_PAIR_AUTO, AC_PAIR_OFF = 0, 1
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
     AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP, AC_TABLE_PAIR, \
     AC_TABLE_GATE_BITS, AC_TABLE_GATE_NODE, AC_TABLE_PATH_OFF, AC_TABLE_PATH_IDS, \
-    AC_TABLE_GATE2_BITS = range(15)
+    AC_TABLE_GATE2_BITS, AC_TABLE_QGATE_BITS, AC_TABLE_QGATE_TAB = range(17)
 
 _TABLE_DTYPE = {AC_TABLE_HOT_DFA: np.uint16, AC_TABLE_HOT_GO: np.uint16, AC_TABLE_CMAP: np.uint8}
 
@@ -132,6 +132,8 @@ SIGNATURES = {
                                       ctypes.POINTER(ac_scan_opts), _vp]),
     "ac_sort_scratch_bytes": (_u64, [_u64]),
     "ac_sort_matches": (ctypes.c_int, [_vp, _u64, _vp, _u64, _vp]),
+    "ac_hbm_read": (ctypes.c_int, [_vp, _u64, _vp, _u32, _vp]),
+    "ac_hbm_copy": (ctypes.c_int, [_vp, _vp, _u64, _u32, _vp]),
     "ac_batch_create": (ctypes.c_int, [_vp, _u32, _vp, _vp, _vp, _u32, ctypes.POINTER(ac_batch_tune),
                                        _vp, ctypes.POINTER(_vp)]),
     "ac_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ac_batch_info_t)]),
@@ -467,6 +469,18 @@ def ac_scan_batch_noalloc(autos, d_texts, d_text_off, d_text_auto, d_matches, ca
     device allocation; at most 65,536 texts; calls on one GPU must not overlap)."""
     _scan_batch("ac_scan_batch_noalloc", autos, d_texts, d_text_off, d_text_auto, d_matches, capacity, d_count,
                 d_match_text, tune, stream)
+
+
+def ac_hbm_read(d, n: int, d_fold, blocks: int = 0, stream=None) -> None:
+    """Stream n bytes of device tensor d once, XOR-folding 32-bit words into
+    d_fold (one int64 element); its time is the HBM read ceiling."""
+    _check(load_library().ac_hbm_read(_ptr(d), n, _ptr(d_fold), blocks, _stream(stream)))
+
+
+def ac_hbm_copy(dst, src, n: int, blocks: int = 0, stream=None) -> None:
+    """Copy n bytes between device tensors with the scans' load shape (a
+    kernel of known traffic for scaling byte counters)."""
+    _check(load_library().ac_hbm_copy(_ptr(dst), _ptr(src), n, blocks, _stream(stream)))
 
 
 def pack_texts(texts, align: int = 16) -> tuple[np.ndarray, np.ndarray, np.ndarray]:

@@ -26,7 +26,7 @@ CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", f"-I{
 HIP_SOURCES = ["dfa_place_hot.hip", "dfa_place_hot_k2.hip", "dfa_place_hot_k3.hip", "dfa_place_hot_k4.hip",
                "dfa_batch_hot_k2.hip", "dfa_batch_hot_k3.hip", "dfa_batch_hot_k4.hip", "dfa_place_hot_pair.hip", "dfa_place_full.hip", "dfa_place_global.hip", "dfa_batch_hot.hip",
                "dfa_batch_global.hip", "dfa.hip", "batch.hip", "serve.hip",
-               "scan.hip", "gate.hip", "api.hip"]
+               "scan.hip", "gate.hip", "qgate.hip", "measure.hip", "api.hip"]
 CXX_SOURCES = ["machine.cpp"]
 
 

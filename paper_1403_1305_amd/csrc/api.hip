@@ -174,6 +174,8 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
     dm.hash_shift = m.hash_shift;
     std::memcpy(dm.hash_letter, m.hash_letter, sizeof(dm.hash_letter));
     dm.gate_pass = m.gate_pass;
+    dm.qg_tab_bits = m.qg_tab_bits;
+    dm.no_class = m.sigma == 256 ? 0x100u : uint32_t(acm::kNoClass);
     std::vector<uint8_t> cmap(m.cmap, m.cmap + 256);
     if ((rc = upload_dfa(a, m, dm, s)) || (rc = upload(a, m.go, &dm.go, s)) ||
         (rc = upload(a, m.out_off, &dm.out_off, s)) || (rc = upload(a, m.out_ids, &dm.out_ids, s)) ||
@@ -181,7 +183,8 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
         (rc = upload(a, m.hot_dfa, &dm.hot_dfa, s)) || (rc = upload(a, m.hot_go, &dm.hot_go, s)) ||
         (rc = upload(a, cmap, &dm.cmap, s)) || (rc = upload(a, m.gate_bits, &dm.gate_bits, s)) || (rc = upload(a, m.gate2_bits, &dm.gate2_bits, s)) ||
         (rc = upload(a, m.gate_node, &dm.gate_node, s)) || (rc = upload(a, m.path_off, &dm.path_off, s)) ||
-        (rc = upload(a, m.path_ids, &dm.path_ids, s)) || (rc = upload(a, m.pat_len, &dm.pat_len, s))) {
+        (rc = upload(a, m.path_ids, &dm.path_ids, s)) || (rc = upload(a, m.pat_len, &dm.pat_len, s)) ||
+        (rc = upload(a, m.qg_bits, &dm.qg_bits, s)) || (rc = upload(a, m.qg_tab, &dm.qg_tab, s))) {
         (void)hipStreamSynchronize(s);
         release(a);
         delete a;
@@ -231,7 +234,7 @@ int ac_info(const ac_automaton *a, ac_info_t *info) {
     info->pair_states = a->m.pair_states;
     info->out_entries = a->m.out_ids.size();
     info->build_ms = a->m.build_ms;
-    info->has_gate = a->m.gate_bits.empty() ? 0u : 1u;
+    info->has_gate = !a->m.gate_bits.empty() ? 1u : !a->m.qg_bits.empty() ? 2u : 0u;
     info->gate_pass = a->m.gate_pass;
     return AC_OK;
 }
@@ -258,6 +261,8 @@ int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_
         case AC_TABLE_PATH_OFF: src = m.path_off.data(); sz = m.path_off.size() * 4; break;
         case AC_TABLE_PATH_IDS: src = m.path_ids.data(); sz = m.path_ids.size() * 4; break;
         case AC_TABLE_GATE2_BITS: src = m.gate2_bits.data(); sz = m.gate2_bits.size() * 4; break;
+        case AC_TABLE_QGATE_BITS: src = m.qg_bits.data(); sz = m.qg_bits.size() * 4; break;
+        case AC_TABLE_QGATE_TAB: src = m.qg_tab.data(); sz = m.qg_tab.size() * 4; break;
         default: return fail(AC_ERR_INVALID, "ac_get_table: unknown table");
     }
     *bytes = sz;
@@ -292,7 +297,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
     if (cfg.algo == AC_ALGO_AUTO) cfg.algo = acm::auto_algo(a);
     if (cfg.algo == AC_ALGO_DFA && a->m.goto_only)
         return fail(AC_ERR_INVALID, "ac_scan: a goto-only automaton has no DFA (use AC_ALGO_PFAC or AC_ALGO_GATED)");
-    if (cfg.algo == AC_ALGO_GATED && !a->dm.gate_bits)
+    if (cfg.algo == AC_ALGO_GATED && !a->dm.gate_bits && !a->dm.qg_bits)
         return fail(AC_ERR_INVALID, "ac_scan: this automaton has no start-position gate (AC_ALGO_GATED)");
     if (!resolve_placement(a, want, cfg.placement))
         return fail(AC_ERR_INVALID, "ac_scan: placement not available for this automaton");
@@ -305,7 +310,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         if (cfg.algo == AC_ALGO_DFA)
             rc = acm::launch_dfa_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
         else if (cfg.algo == AC_ALGO_GATED)
-            rc = acm::launch_gate_scan(a->dm, d_text, n, d_matches, capacity, d_count, s, err);
+            rc = acm::launch_gated_scan(a->dm, d_text, n, d_matches, capacity, d_count, s, err);
         else
             rc = acm::launch_pfac_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
     }

@@ -26,7 +26,7 @@ int set_error(int code, const std::string &msg);
 // DFA's lookup per byte, else the DFA (the failure-less scan without DFA).
 constexpr double kGateAutoPass = 0.05;
 inline uint32_t auto_algo(const ac_automaton *a) {
-    if (a->dm.gate_bits && a->m.gate_pass <= kGateAutoPass) return AC_ALGO_GATED;
+    if ((a->dm.gate_bits || a->dm.qg_bits) && a->m.gate_pass <= kGateAutoPass) return AC_ALGO_GATED;
     return a->m.goto_only ? AC_ALGO_PFAC : AC_ALGO_DFA;
 }
 }  // namespace acm

@@ -38,8 +38,6 @@
 namespace acm {
 namespace dfa {
 
-constexpr uint32_t kNoClassDev = 0xffu;
-
 struct DfaArgs {
     const uint8_t *text;
     uint32_t n;            // text bytes (< 2^32)
@@ -53,6 +51,7 @@ struct DfaArgs {
     uint32_t hash_shift;   // hashed classes: column = (b >> shift) & (n_cols - 1)
     uint32_t pair_base;    // word of dfa where the two-byte rows of states >= hot start
     uint32_t letters_lo, letters_hi;  // the letter owning each hashed column
+    uint32_t no_class;     // byte-map value of bytes in no pattern (DeviceMachine::no_class)
     const uint32_t *dfa;
     const uint16_t *hot_rows;
     const uint8_t *cmap;
@@ -94,7 +93,7 @@ __device__ __forceinline__ uint32_t step_byte(uint32_t s, uint32_t b, const DfaA
                                               const uint8_t *s_cmap, const uint32_t *s_tab,
                                               const uint16_t *s_hot) {
     const uint32_t c = s_cmap[b];
-    const bool valid = c != kNoClassDev;
+    const bool valid = c != a.no_class;
     const uint32_t e = lookup<PLACE, LOG2C>(s & kStateMask, valid ? c : 0u, a, s_tab, s_hot);
     return valid ? e : 0u;
 }
@@ -660,6 +659,7 @@ inline void fill_machine_args(const DeviceMachine &dm, DfaArgs &a) {
     a.dfa = dm.dfa;
     a.hot_rows = dm.hot_dfa;
     a.cmap = dm.cmap;
+    a.no_class = dm.no_class;
     a.out_off = dm.out_off;
     a.out_ids = dm.out_ids;
 }

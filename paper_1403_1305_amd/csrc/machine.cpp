@@ -175,6 +175,63 @@ void build_gate(Machine &m, const uint8_t *pat, const uint64_t *off) {
     }
 }
 
+// The hashed start-position gate (see Machine::qg_bits), from the goto
+// function; every pattern is at least kQgQ bytes long.
+void build_qgate(Machine &m, const uint8_t *pat, const uint64_t *off) {
+    const uint32_t n = m.n_patterns, C = m.n_cols;
+    struct Win {
+        uint32_t x, y, node;
+    };
+    std::vector<Win> wins;
+    wins.reserve(n);
+    std::vector<uint64_t> freq(256, 0);
+    uint64_t total = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint8_t *p = pat + off[k];
+        for (uint64_t i = 0; i < off[k + 1] - off[k]; ++i) ++freq[p[i]];
+        total += off[k + 1] - off[k];
+        uint32_t x = 0;
+        for (uint32_t d = 0; d < kQgQ; ++d) x = m.go[size_t(x) * C + m.cmap[p[d]]] & kStateMask;
+        wins.push_back({uint32_t(p[0]) | uint32_t(p[1]) << 8 | uint32_t(p[2]) << 16,
+                        uint32_t(p[3]) | uint32_t(p[4]) << 8 | uint32_t(p[5]) << 16, x});
+    }
+    std::sort(wins.begin(), wins.end(), [](const Win &a, const Win &b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
+    wins.erase(std::unique(wins.begin(), wins.end(), [](const Win &a, const Win &b) { return a.x == b.x && a.y == b.y; }),
+               wins.end());
+    m.qg_bits.assign(kQgWords, 0u);
+    uint32_t bits = 8;
+    while ((1ull << bits) < 2ull * wins.size()) ++bits;
+    m.qg_tab_bits = bits;
+    m.qg_tab.assign(size_t(4) << bits, 0u);
+    const uint32_t mask = (1u << bits) - 1u;
+    double cover = 0.0;
+    for (const Win &w : wins) {
+        const uint32_t h = qg_hash(w.x, w.y);
+        m.qg_bits[qg_word(h)] |= qg_mask(h);
+        uint32_t slot = qg_slot_hash(w.x, w.y) >> (32 - bits);
+        while (m.qg_tab[size_t(slot) * 4 + 1] & kQgUsed) slot = (slot + 1) & mask;
+        uint32_t *e = &m.qg_tab[size_t(slot) * 4];
+        e[0] = w.x | (w.y & 0xffu) << 24;
+        e[1] = w.y >> 8 | kQgUsed;
+        e[2] = w.node;
+        e[3] = m.own_off[w.node + 1] > m.own_off[w.node] ? 1u : 0u;
+        double pr = 1.0;
+        for (uint32_t d = 0; d < 3; ++d)
+            pr *= double(freq[(w.x >> (8 * d)) & 0xffu]) * double(freq[(w.y >> (8 * d)) & 0xffu]) /
+                  (double(total) * double(total));
+        cover += pr;
+    }
+    // a window that begins no pattern passes when both of its bits are set:
+    // about the mean over words of (set bits / 32)^2
+    double fp = 0.0;
+    for (uint32_t w : m.qg_bits) {
+        const double f = double(__builtin_popcount(w)) / 32.0;
+        fp += f * f;
+    }
+    fp /= double(kQgWords);
+    m.gate_pass = std::min(1.0, cover + (1.0 - std::min(1.0, cover)) * fp);
+}
+
 }  // namespace
 
 int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const HotPlan &plan,
@@ -524,8 +581,17 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     m.path_off.clear();
     m.path_ids.clear();
     m.pat_len.clear();
+    m.qg_bits.clear();
+    m.qg_tab.clear();
+    m.qg_tab_bits = 0;
     m.gate_pass = 1.0;
-    if (plan.gate && m.hashed && C == 4 && S - 1 <= kGateNodeMask) build_gate(m, pat, off);
+    if (plan.gate && m.hashed && C == 4 && S - 1 <= kGateNodeMask) {
+        build_gate(m, pat, off);
+    } else if (plan.gate) {
+        uint64_t shortest = ~0ull;
+        for (uint32_t k = 0; k < n; ++k) shortest = std::min<uint64_t>(shortest, off[k + 1] - off[k]);
+        if (n > 0 && shortest >= kQgQ) build_qgate(m, pat, off);
+    }
     // 16-bit images are copied as 32-bit words: pad them to whole words
     if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);
     if (m.hot_go.size() & 1) m.hot_go.push_back(0);

@@ -47,6 +47,23 @@ constexpr uint32_t kGate2Bits = 1u << 16;
 // lowest two bits): the top 16 bits of a multiplicative hash.
 inline constexpr uint32_t gate2_hash(uint32_t code24) { return (code24 * 0x9E3779B1u) >> 16; }
 
+// Hashed start-position gate (machines whose patterns are all at least kQgQ
+// bytes long and that have no class gate). A window is the kQgQ bytes from a
+// start position on, read as X = bytes 0..2 and Y = bytes 3..5 (each little
+// endian, 24 bits). qg_hash(X, Y) picks a word of a 2^20-bit bitmap (bits 17
+// and up) and two bits in it (bits 12..16 and 7..11): a blocked Bloom filter
+// over the windows that begin some pattern. A table of those windows,
+// open-addressed by qg_slot_hash, gives the goto state each one leads to.
+constexpr uint32_t kQgQ = 6;
+constexpr uint32_t kQgWords = 1u << 15;
+constexpr uint32_t kQgK1 = 0x9E3779u, kQgK2 = 0x85EBCBu;  // odd, below 2^24
+constexpr uint32_t kQgK3 = 0xC2B2AFu, kQgK4 = 0x27D4EBu;
+constexpr uint32_t kQgUsed = 0x80000000u;  // table entry word 1: slot in use
+inline constexpr uint32_t qg_hash(uint32_t x, uint32_t y) { return x * kQgK1 ^ y * kQgK2; }
+inline constexpr uint32_t qg_slot_hash(uint32_t x, uint32_t y) { return x * kQgK3 ^ y * kQgK4; }
+inline constexpr uint32_t qg_word(uint32_t h) { return h >> 17; }
+inline constexpr uint32_t qg_mask(uint32_t h) { return 1u << ((h >> 12) & 31u) | 1u << ((h >> 7) & 31u); }
+
 struct Machine {
     uint32_t n_patterns = 0;
     uint32_t m_max = 0;
@@ -104,7 +121,22 @@ struct Machine {
     //              string y of kGateQ2 bytes a pattern can begin with (its
     //              first kGateQ2 classes, or every extension of a shorter one);
     std::vector<uint32_t> gate_bits, gate2_bits, gate_node, path_off, path_ids, pat_len;
-    double gate_pass = 1.0;  // fraction of codes whose bit is set
+    // Hashed gate (empty unless built; never beside the class gate):
+    //   qg_bits  kQgWords words, the blocked Bloom filter: for the window
+    //            (X, Y) of every pattern's first kQgQ bytes, both bits of
+    //            qg_mask(h) are set in word qg_word(h), h = qg_hash(X, Y);
+    //   qg_tab   2^qg_tab_bits slots of 4 words, one per distinct window:
+    //            {X | (Y & 0xff) << 24, Y >> 8 | kQgUsed, goto state the
+    //            window leads to from the root, 1 if patterns end there};
+    //            a window's slot is the first free one from the top
+    //            qg_tab_bits bits of qg_slot_hash(X, Y) on, wrapping.
+    std::vector<uint32_t> qg_bits, qg_tab;
+    uint32_t qg_tab_bits = 0;
+    // Expected fraction of start positions the gate passes: for the class
+    // gate, the share of window codes whose bit is set; for the hashed gate,
+    // the chance that a window drawn from the patterns' byte frequencies
+    // begins a pattern, plus the filter's false-positive rate.
+    double gate_pass = 1.0;
     double build_ms = 0.0;
 };
 

@@ -1,0 +1,293 @@
+// qgate.hip -- the failure-less scan from start positions a hashed gate passes
+// (AC_ALGO_GATED on machines without the class gate whose patterns are all
+// at least kQgQ bytes long).
+//
+// Every occurrence begins at exactly one start position, and the failure-less
+// machine (the goto function with the patterns that end at each state, the
+// paper's Sec. II.B and IV.A) walked from there finds every pattern that
+// begins at it. A pattern can begin at p only if the kQgQ bytes from p are
+// the first kQgQ bytes of some pattern. A blocked Bloom filter over those
+// windows, 2^20 bits in LDS, tests each start with one LDS read: two bits of
+// one word, picked by a multiplicative hash of the window. A start that
+// passes is looked up in a hash table of the windows (in global memory, small
+// enough to stay in L2), which rejects the filter's false positives and gives
+// the goto state after the window; the walk goes on from there.
+//
+// A wave step reads 1 KiB of text, 16 bytes per lane in one coalesced load,
+// and owns the last 1008 of them: lane 0 holds the 16 bytes before, so that
+// every lane finds the 5 bytes before its own in the lane below and tests the
+// 16 windows that end in its bytes. Steps are handed to the waves of the grid
+// in turn. Passing starts go to a per-wave queue in LDS; whenever 63 or more
+// wait, the wave looks up and walks up to 64 of them, one per lane. Starts in
+// the last kQgQ - 1 bytes of the text begin no pattern and are not tested.
+#include <algorithm>
+#include <utility>
+
+#include "device_common.h"
+#include "machine.h"
+#include "scan.h"
+
+namespace acm {
+namespace {
+
+constexpr uint32_t kQgBlock = 1024;
+constexpr uint32_t kQgWaves = kQgBlock / 64;
+constexpr uint32_t kLaneBytes = 16;
+constexpr uint32_t kOwnBytes = 63 * kLaneBytes;  // text a wave step owns
+constexpr uint32_t kPrefetch = 4;                // wave steps loaded ahead
+constexpr uint32_t kStartQueue = 128;            // queued start positions per wave (at most 62 + 63)
+constexpr uint32_t kQgLds = kQgWords * 4 + 256 + kQgWaves * (kStartQueue * 4 + kQueueBytesPerWave);
+static_assert(kQgLds <= kLdsPerWorkgroup, "hashed gate kernel LDS");
+static_assert(kQgQ == 6, "the window extraction below assumes 6-byte windows");
+
+struct QgArgs {
+    const uint8_t *text;
+    uint32_t n;
+    uint32_t n_cols;
+    const uint32_t *bits;  // kQgWords words
+    const uint4 *tab;      // the window table
+    uint32_t tab_shift;    // 32 - log2 of its slots
+    uint32_t tab_mask;     // slots - 1
+    uint32_t no_class;     // byte-map value of bytes in no pattern
+    const uint32_t *go, *own_off, *own_ids;
+    const uint8_t *cmap;
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+};
+
+// Low 32 bits of the product of the low 24 bits of a and b (one full-rate
+// multiply). HIP's __umul24 returns int, which would make a later right
+// shift arithmetic; this returns the unsigned value.
+__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) { return uint32_t(__umul24(a, b)); }
+
+// 16 bytes the text streams past once (non-temporal: they need not stay in
+// the caches, which then keep the walks' tables).
+__device__ __forceinline__ uint4 load_stream(const uint8_t *p) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(x[0], x[1], x[2], x[3]);
+}
+
+// Goto walks from state x of the lanes with `active`, over the bytes from i
+// on: each step into a state where patterns end reports them at that byte.
+// A walk ends at the first missing edge, a byte in no pattern or the end of
+// the text.
+__device__ __forceinline__ void walk_on(const QgArgs &a, const uint8_t *s_cmap, bool active, uint32_t x,
+                                        uint32_t i, Emitter &em) {
+    while (__any(active)) {
+        uint32_t g = 0;
+        if (active) {
+            if (i >= a.n) {
+                active = false;
+            } else {
+                const uint32_t c = s_cmap[a.text[i]];
+                g = c != a.no_class ? a.go[x * a.n_cols + c] : 0u;
+                active = g != 0u;
+                if (active) x = g & kStateMask;
+            }
+        }
+        emit_set(em, active && (g & kAccept), x, i, a.own_off, a.own_ids);
+        ++i;
+    }
+}
+
+// Look up the windows at the start positions p (lanes with `has`; p + kQgQ
+// <= n) in the table and walk on from the states of those found.
+__device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cmap, bool has, uint32_t p,
+                                            Emitter &em) {
+    bool hit = false;
+    uint32_t x = 0, own = 0;
+    if (has) {
+        const uint32_t *t = reinterpret_cast<const uint32_t *>(a.text);
+        const uint32_t last = (a.n - 1u) >> 2, i0 = p >> 2, sh = p & 3u;
+        const uint32_t w0 = t[i0], w1 = t[min(i0 + 1u, last)], w2 = t[min(i0 + 2u, last)];
+        // bytes p .. p + 3 and p + 4 .. p + 7 (those at or past n unused)
+        const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
+        const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
+        const uint32_t wx = lo & 0xffffffu, wy = (lo >> 24) | (hi & 0xffffu) << 8;
+        const uint32_t k1 = (hi & 0xffffu) | kQgUsed;
+        uint32_t slot = (mul_u24(wx, kQgK3) ^ mul_u24(wy, kQgK4)) >> a.tab_shift;
+        while (true) {
+            const uint4 e = a.tab[slot];
+            if (!(e.y & kQgUsed)) break;
+            if (e.x == lo && e.y == k1) {
+                hit = true;
+                x = e.z;
+                own = e.w;
+                break;
+            }
+            slot = (slot + 1u) & a.tab_mask;
+        }
+    }
+    emit_set(em, hit && own, x, p + kQgQ - 1u, a.own_off, a.own_ids);
+    walk_on(a, s_cmap, hit, x, p + kQgQ, em);
+}
+
+// Walk up to 64 of the qn starts queued at q, one per lane; returns how many
+// wait afterwards.
+__device__ __forceinline__ uint32_t drain_starts(const QgArgs &a, const uint8_t *s_cmap, const uint32_t *q,
+                                                 uint32_t qn, Emitter &em) {
+    const uint32_t lane = __lane_id();
+    const uint32_t took = min(qn, 64u);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t p = lane < took ? q[qn - took + lane] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    walk_starts(a, s_cmap, lane < took, p, em);
+    return qn - took;
+}
+
+// Four bytes from byte o of the lane's window registers r (r[0] holds bytes
+// -8 .. -5, ..., r[5] bytes 12 .. 15; o + 3 may pass byte 15, those bytes are
+// unused).
+template <int O>
+__device__ __forceinline__ uint32_t bytes_at(const uint32_t (&r)[6]) {
+    constexpr int k = (O + 8) >> 2, sh = (O + 8) & 3;
+    if constexpr (sh == 0) return r[k];
+    else return __builtin_amdgcn_alignbyte(r[k + 1 < 6 ? k + 1 : 5], r[k], sh);
+}
+
+template <int J>
+__device__ __forceinline__ uint32_t test_window(const uint32_t *s_bits, const uint32_t (&r)[6]) {
+    // the window ending at byte J: X = bytes J-5 .. J-3, Y = bytes J-2 .. J
+    const uint32_t h = mul_u24(bytes_at<J - 5>(r), kQgK1) ^ mul_u24(bytes_at<J - 2>(r), kQgK2);
+    const uint32_t word = s_bits[h >> 17];
+    // bits (h >> 12) mod 32 and (h >> 7) mod 32 (the field offsets take the
+    // low 5 bits)
+    return (__builtin_amdgcn_ubfe(word, h >> 12, 1u) & __builtin_amdgcn_ubfe(word, h >> 7, 1u)) << J;
+}
+
+template <int... J>
+__device__ __forceinline__ uint32_t test_windows(const uint32_t *s_bits, const uint32_t (&r)[6],
+                                                 std::integer_sequence<int, J...>) {
+    return (test_window<J>(s_bits, r) | ...);
+}
+
+// The windows of one wave step. Lane l (l >= 1) owns the 16 bytes at pos (v);
+// P2, P3 are the last 8 bytes of the lane below. `valid` masks the windows
+// (by their last byte) that lie inside the text. Passing starts are queued at
+// q (qn of them waiting, the same in every lane); whenever 63 or more wait (a
+// queue below 63 takes a round's at most 63 new ones) up to 64 are walked.
+__device__ __forceinline__ void step_windows(const QgArgs &a, const uint32_t *s_bits, const uint8_t *s_cmap,
+                                             const uint4 &v, uint32_t P2, uint32_t P3, uint32_t pos, uint32_t valid,
+                                             uint32_t *q, uint32_t &qn, Emitter &em) {
+    const uint32_t r[6] = {P2, P3, v.x, v.y, v.z, v.w};
+    uint32_t m = test_windows(s_bits, r, std::make_integer_sequence<int, 16>()) & valid;
+    while (true) {
+        const uint64_t has = __ballot(m != 0);
+        if (has == 0) break;
+        uint32_t p = 0;
+        if (m) {
+            const uint32_t j = uint32_t(__builtin_ctz(m));
+            m &= m - 1u;
+            p = pos + j - (kQgQ - 1u);
+            q[qn + lane_rank(has)] = p;
+        }
+        qn += uint32_t(__popcll(has));
+        if (qn >= 63) qn = drain_starts(a, s_cmap, q, qn, em);
+    }
+}
+
+__global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
+    // static LDS: the bitmap's address is then a constant the lookups fold in
+    __shared__ __align__(16) uint32_t s_bits[kQgWords];
+    __shared__ __align__(16) uint8_t s_cmap[256];
+    __shared__ __align__(16) uint32_t s_queue[kQgWaves * kStartQueue];
+    __shared__ __align__(16) uint8_t s_emit[kQgWaves * kQueueBytesPerWave];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x & 63u;
+    Emitter em;
+    em.init(s_emit, a.out, a.cap, a.count);
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.bits);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
+        for (uint32_t i = threadIdx.x; i < kQgWords / 4; i += kQgBlock) dst[i] = src[i];
+        if (threadIdx.x < 256) s_cmap[threadIdx.x] = a.cmap[threadIdx.x];
+    }
+    __syncthreads();
+    uint32_t *q = s_queue + wave * kStartQueue;
+    uint32_t qn = 0;  // queued starts (the same in every lane)
+
+    const uint32_t W = gridDim.x * kQgWaves, gw = blockIdx.x * kQgWaves + wave;
+    const uint32_t n_tiles = uint32_t((uint64_t(a.n) + kOwnBytes - 1) / kOwnBytes);
+    // tiles whose 1 KiB lies inside the text, the first excepted (its lane 0
+    // would read before byte 0): t = first, first + W, ... < full
+    const uint32_t full = a.n / kOwnBytes;
+    const uint32_t first = gw == 0 ? W : gw;
+    const uint32_t cnt = full > first ? (full - first + W - 1) / W : 0u;
+    const uint8_t *lane_text = a.text + lane * kLaneBytes;  // + t * kOwnBytes - 16
+    uint4 buf[kPrefetch];  // the next kPrefetch tiles of this wave, in flight
+#pragma unroll
+    for (uint32_t k = 0; k < kPrefetch; ++k)
+        buf[k] = k < cnt ? load_stream(lane_text + (first + k * W) * kOwnBytes - 16) : make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t i = 0; i < cnt; i += kPrefetch) {
+#pragma unroll
+        for (uint32_t k = 0; k < kPrefetch; ++k) {
+            if (i + k >= cnt) break;
+            const uint32_t t = first + (i + k) * W;
+            const uint4 v = buf[k];
+            if (i + k + kPrefetch < cnt) buf[k] = load_stream(lane_text + (t + kPrefetch * W) * kOwnBytes - 16);
+            const uint32_t P2 = __shfl_up(v.z, 1), P3 = __shfl_up(v.w, 1);
+            const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
+            step_windows(a, s_bits, s_cmap, v, P2, P3, pos, lane ? 0xffffu : 0u, q, qn, em);
+        }
+    }
+    // the first tile and a last, partial one: loads and windows checked
+    // against the text's ends
+    for (uint32_t e = 0; e < 2; ++e) {
+        const uint32_t t = e == 0 ? 0u : n_tiles - 1u;
+        if (n_tiles == 0 || (e == 1 && (t < full || t == 0)) || gw != t % W) continue;
+        const int64_t base = int64_t(t) * kOwnBytes - 16 + int64_t(lane) * kLaneBytes;
+        const uint4 v = base >= 0 && base < int64_t(a.n) ? *reinterpret_cast<const uint4 *>(a.text + base)
+                                                          : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t P2 = __shfl_up(v.z, 1), P3 = __shfl_up(v.w, 1);
+        // window ends base + j must lie in [kQgQ - 1, n)
+        uint32_t valid = 0;
+        if (lane > 0) {
+            for (uint32_t j = 0; j < 16; ++j)
+                if (base + j >= kQgQ - 1 && base + j < int64_t(a.n)) valid |= 1u << j;
+        }
+        step_windows(a, s_bits, s_cmap, v, P2, P3, uint32_t(base), valid, q, qn, em);
+    }
+    if (qn) drain_starts(a, s_cmap, q, qn, em);
+    em.flush();
+}
+
+}  // namespace
+
+int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
+                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err) {
+    if (!dm.qg_bits) {
+        err = "ac_scan: this automaton has no hashed start-position gate";
+        return AC_ERR_INVALID;
+    }
+    if (uint64_t(dm.n_states) * dm.n_cols >= (1ull << 32)) {
+        err = "ac_scan: goto table too large for the gated scan's 32-bit indexing";
+        return AC_ERR_TOO_LARGE;
+    }
+    if (n < kQgQ) return AC_OK;  // no start has a whole window: nothing can match
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const uint32_t cus = uint32_t(compute_units(dev));
+    QgArgs a{};
+    a.text = text;
+    a.n = uint32_t(n);
+    a.n_cols = dm.n_cols;
+    a.bits = dm.qg_bits;
+    a.tab = reinterpret_cast<const uint4 *>(dm.qg_tab);
+    a.tab_shift = 32u - dm.qg_tab_bits;
+    a.tab_mask = (1u << dm.qg_tab_bits) - 1u;
+    a.go = dm.go;
+    a.own_off = dm.own_off;
+    a.own_ids = dm.own_ids;
+    a.cmap = dm.cmap;
+    a.no_class = dm.no_class;
+    a.out = out;
+    a.cap = cap;
+    a.count = reinterpret_cast<unsigned long long *>(count);
+    // one workgroup per CU (the bitmap fills most of the LDS), fewer for short texts
+    const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
+    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kQgWaves - 1) / kQgWaves, cus)));
+    return launch_kernel(qgate_kernel, grid, kQgBlock, 0u, stream, a, err);
+}
+
+}  // namespace acm

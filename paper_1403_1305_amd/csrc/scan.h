@@ -14,6 +14,10 @@ struct DeviceMachine {
     uint32_t n_states = 0, n_cols = 0, m_max = 0, hot_states = 0;
     uint32_t term_end = 0, acc_end = 0;  // state id ranges (see Machine)
     uint32_t log2_cols = 0, hash_shift = 0;
+    // Value of a byte-map entry for bytes in no pattern: 0xff, or 0x100 (which
+    // no entry equals) when every byte value occurs in some pattern and the
+    // 256 columns use all entry values.
+    uint32_t no_class = 0xffu;
     bool cols_pow2 = false, hashed = false;
     uint8_t hash_letter[8] = {0};
     const uint32_t *dfa = nullptr, *go = nullptr;
@@ -28,6 +32,9 @@ struct DeviceMachine {
     // NULL when the machine has none.
     const uint32_t *gate_bits = nullptr, *gate2_bits = nullptr, *gate_node = nullptr;
     const uint32_t *path_off = nullptr, *path_ids = nullptr, *pat_len = nullptr;
+    // Hashed gate (Machine::qg_bits, qg_tab); qg_bits is NULL without it.
+    const uint32_t *qg_bits = nullptr, *qg_tab = nullptr;
+    uint32_t qg_tab_bits = 0;
     double gate_pass = 1.0;
 };
 
@@ -68,6 +75,16 @@ int launch_copy_state(const uint32_t *in, uint32_t *out, hipStream_t stream, std
 // must be set).
 int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err);
+// Failure-less walks from the start positions the hashed gate passes
+// (dm.qg_bits must be set).
+int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
+                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err);
+// The gated scan with whichever gate the machine has.
+inline int launch_gated_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
+                             uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err) {
+    return dm.gate_bits ? launch_gate_scan(dm, text, n, out, cap, count, stream, err)
+                        : launch_qgate_scan(dm, text, n, out, cap, count, stream, err);
+}
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                      std::string &err);

@@ -17,8 +17,6 @@
 namespace acm {
 namespace {
 
-constexpr uint32_t kNoClassDev = 0xffu;
-
 __global__ void zero_count_kernel(unsigned long long *count) { *count = 0ull; }
 
 // ------------------------------------------------------------------ PFAC scan
@@ -31,6 +29,7 @@ struct PfacArgs {
     uint32_t term_lo, term_end;  // states where a pattern ends exactly
     uint32_t table_words;
     uint32_t halo;  // text bytes staged past the tile's last start
+    uint32_t no_class;  // byte-map value of bytes in no pattern
     const uint32_t *go;
     const uint16_t *hot;
     const uint8_t *cmap;
@@ -99,7 +98,7 @@ __global__ void __launch_bounds__(BLOCK) pfac_scan_kernel(PfacArgs a) {
             for (uint64_t j = p; j < a.n; ++j) {
                 const uint64_t t = j - base;
                 const uint32_t c = t < staged ? s_cls[t] : s_cmap[a.text[j]];
-                if (c == kNoClassDev) break;
+                if (c == a.no_class) break;
                 const uint32_t e = go_entry<PLACE>(s, c, a, s_tab, s_hot);
                 if (e == 0) break;
                 s = e & kStateMask;
@@ -285,6 +284,7 @@ int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     a.go = dm.go;
     a.hot = dm.hot_go;
     a.cmap = dm.cmap;
+    a.no_class = dm.no_class;
     a.own_off = dm.own_off;
     a.own_ids = dm.own_ids;
     a.out = out;

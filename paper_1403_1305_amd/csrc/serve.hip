@@ -131,7 +131,7 @@ public:
         int rc = AC_OK;
         if (acm::auto_algo(a) == AC_ALGO_GATED) {
             *pieces = 1;
-            rc = acm::launch_gate_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err);
+            rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err);
         } else {
             acm::ScanConfig cfg;
             cfg.algo = AC_ALGO_DFA;

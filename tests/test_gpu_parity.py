@@ -306,6 +306,10 @@ def test_full_protein1g_dfa():
     check_full("protein1g", device_sort=True)
 
 
+def test_full_protein1g_gated():
+    check_full("protein1g", algo=ac.AC_ALGO_GATED, device_sort=True)
+
+
 # ---------------------------------------------------------------- streaming (carried state)
 
 def stream_scan(auto, text: np.ndarray, cuts, opts=None):

@@ -399,8 +399,13 @@ def test_gate_only_where_it_applies():
     assert ac.ac_info(build_host([b"ACGTACGTACGT"]))["has_gate"] == 1
     assert ac.ac_info(build_host([b"ACGTACGTACGT"], flags=ac.AC_BUILD_NO_GATE))["has_gate"] == 0
     assert ac.ac_info(build_host([b"ACGTACGTACGT"], flags=ac.AC_BUILD_GOTO_ONLY))["has_gate"] == 1
+    # other alphabets: the hashed gate, when every pattern has 6 bytes or more
     prot = ac.ac_info(build_host([PROTEIN[:8], PROTEIN[5:]]))
-    assert prot["has_gate"] == 0 and prot["gate_pass"] == 1.0
+    assert prot["has_gate"] == 2 and prot["gate_pass"] < 0.01
+    short = ac.ac_info(build_host([PROTEIN[:5], PROTEIN[5:]]))
+    assert short["has_gate"] == 0 and short["gate_pass"] == 1.0
+    assert ac.ac_info(build_host([PROTEIN[:8]], flags=ac.AC_BUILD_NO_GATE))["has_gate"] == 0
+    assert ac.ac_info(build_host([PROTEIN[:8]], flags=ac.AC_BUILD_GOTO_ONLY))["has_gate"] == 2
     # a 3-letter alphabet in a 2-bit field: the fourth class has no letter
     three = ac.ac_info(build_host([b"ACGACG", b"GGA"]))
     assert three["n_cols"] == 4 and three["has_gate"] == 1
@@ -408,3 +413,76 @@ def test_gate_only_where_it_applies():
     w = plain_workload("dna256m", n=1 << 20)
     info = ac.ac_info(build_host(w.patterns))
     assert info["has_gate"] == 1 and 0.005 < info["gate_pass"] < 0.02
+
+
+def qgate_window(b: bytes) -> tuple[int, int]:
+    """X and Y of the hashed gate's window: bytes 0..2 and 3..5, little endian."""
+    return b[0] | b[1] << 8 | b[2] << 16, b[3] | b[4] << 8 | b[5] << 16
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_hashed_gate_tables_match_their_definition(seed):
+    """For every pattern's first 6 bytes (X, Y): both bits of the blocked
+    Bloom filter are set, and probing the window table from the window's slot
+    finds an entry holding the window, the goto state its 6 bytes lead to from
+    the root and whether patterns end there. Every entry is some pattern's
+    window, and random windows pass the filter about as often as
+    gate_pass says."""
+    w = plain_workload("protein1g", n=1 << 16)
+    rng = np.random.default_rng(seed)
+    pats = [w.patterns[int(k)] for k in rng.choice(len(w.patterns), 3000, replace=False)]
+    pats += [pats[0][:6], bytes([0, 255, 7, 128, 1, 2, 3])]  # a 6-byte pattern; bytes outside the alphabet
+    a = build_host(pats)
+    info = ac.ac_info(a)
+    assert info["has_gate"] == 2 and info["n_cols"] > 4
+    t = Tables(a)
+    bits = ac.ac_get_table(a, ac.AC_TABLE_QGATE_BITS)
+    tab = ac.ac_get_table(a, ac.AC_TABLE_QGATE_TAB).reshape(-1, 4)
+    assert bits.size == 1 << 15 and tab.shape[0] & (tab.shape[0] - 1) == 0
+    slots = tab.shape[0]
+    log2 = slots.bit_length() - 1
+    M = 0xFFFFFFFF
+
+    def h(x, y):
+        return ((x * 0x9E3779) & M) ^ ((y * 0x85EBCB) & M)
+
+    windows = {}
+    for p in pats:
+        x, y = qgate_window(p[:6])
+        s = 0
+        for b in p[:6]:
+            s = int(t.go[s, t.cmap[b]]) & 0x7FFFFFFF
+        windows[(x, y)] = s
+        hh = h(x, y)
+        word = int(bits[hh >> 17])
+        assert (word >> ((hh >> 12) & 31)) & 1 and (word >> ((hh >> 7) & 31)) & 1, p
+        slot = (((x * 0xC2B2AF) & M) ^ ((y * 0x27D4EB) & M)) >> (32 - log2)
+        while True:
+            e = tab[slot]
+            assert e[1] >> 31, p  # reached an empty slot before the window
+            if int(e[0]) == (x | (y & 255) << 24) and int(e[1]) == (y >> 8) | 1 << 31:
+                break
+            slot = (slot + 1) % slots
+        assert int(e[2]) == s and int(e[3]) == int(t.own_off[s + 1] > t.own_off[s]), p
+    used = tab[(tab[:, 1] >> 31) == 1]
+    assert len(used) == len(windows) and slots >= 2 * len(windows)
+    for e in used:
+        key = (int(e[0]) & 0xFFFFFF, int(e[0]) >> 24 | (int(e[1]) & 0xFFFF) << 8)
+        assert windows[key] == int(e[2])
+    # random windows with the patterns' byte frequencies: pass rate near gate_pass
+    allb = np.frombuffer(b"".join(pats), np.uint8)
+    sample = rng.choice(allb, size=(20000, 6))
+    x = sample[:, 0].astype(np.int64) | sample[:, 1].astype(np.int64) << 8 | sample[:, 2].astype(np.int64) << 16
+    y = sample[:, 3].astype(np.int64) | sample[:, 4].astype(np.int64) << 8 | sample[:, 5].astype(np.int64) << 16
+    hh = ((x * 0x9E3779) & M) ^ ((y * 0x85EBCB) & M)
+    word = bits[hh >> 17].astype(np.int64)
+    passed = ((word >> ((hh >> 12) & 31)) & (word >> ((hh >> 7) & 31)) & 1).mean()
+    assert abs(passed - info["gate_pass"]) < 0.01 + 0.3 * info["gate_pass"], (passed, info["gate_pass"])
+
+
+def test_hashed_gate_for_the_protein_set():
+    """The 50,000-pattern protein set gets the hashed gate, expected to pass
+    a few percent of start positions (below AC_ALGO_AUTO's 1 in 20)."""
+    w = plain_workload("protein1g", n=1 << 16)
+    info = ac.ac_info(build_host(w.patterns))
+    assert info["has_gate"] == 2 and 0.02 < info["gate_pass"] < 0.05
