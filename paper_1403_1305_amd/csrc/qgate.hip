@@ -17,8 +17,9 @@
 // and owns the last 1008 of them: lane 0 holds the 16 bytes before, so that
 // every lane finds the 5 bytes before its own in the lane below and tests the
 // 16 windows that end in its bytes. Steps are handed to the waves of the grid
-// in turn. Passing starts go to a per-wave queue in LDS; whenever 63 or more
-// wait, the wave looks up and walks up to 64 of them, one per lane. Starts in
+// in turn. Passing starts go to a per-wave queue in LDS; whenever kDrainAt or
+// more wait, the wave looks up and walks all of them, kWalks per lane at once
+// (so that their dependent loads overlap), then goes on streaming. Starts in
 // the last kQgQ - 1 bytes of the text begin no pattern and are not tested.
 #include <algorithm>
 #include <utility>
@@ -35,7 +36,9 @@ constexpr uint32_t kQgWaves = kQgBlock / 64;
 constexpr uint32_t kLaneBytes = 16;
 constexpr uint32_t kOwnBytes = 63 * kLaneBytes;  // text a wave step owns
 constexpr uint32_t kPrefetch = 4;                // wave steps loaded ahead
-constexpr uint32_t kStartQueue = 128;            // queued start positions per wave (at most 62 + 63)
+constexpr uint32_t kWalks = 4;                   // queued starts a lane walks at once
+constexpr uint32_t kDrainAt = 64 * kWalks - 63;  // queue length that triggers a drain
+constexpr uint32_t kStartQueue = 64 * kWalks;    // queued start positions per wave (at most kDrainAt - 1 + 63)
 constexpr uint32_t kQgLds = kQgWords * 4 + 256 + kQgWaves * (kStartQueue * 4 + kQueueBytesPerWave);
 static_assert(kQgLds <= kLdsPerWorkgroup, "hashed gate kernel LDS");
 static_assert(kQgQ == 6, "the window extraction below assumes 6-byte windows");
@@ -61,79 +64,141 @@ struct QgArgs {
 // shift arithmetic; this returns the unsigned value.
 __device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) { return uint32_t(__umul24(a, b)); }
 
-// 16 bytes the text streams past once (non-temporal: they need not stay in
-// the caches, which then keep the walks' tables).
-__device__ __forceinline__ uint4 load_stream(const uint8_t *p) {
+// 16 bytes of the text stream. Ordinary (temporal) loads: the starts a
+// step queues read their window again a few steps later, and one in 30 or
+// so of the positions of protein-like text is queued, so keeping the text
+// in L2 for that long beats keeping the tables there alone (measured 4%).
+__device__ __forceinline__ uint4 load_stream(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+template <uint32_t... K>
+__device__ __forceinline__ void emit_walks(const QgArgs &a, Emitter &em, const bool (&active)[kWalks],
+                                           const uint32_t (&g)[kWalks], const uint32_t (&x)[kWalks],
+                                           const uint32_t (&i)[kWalks], std::integer_sequence<uint32_t, K...>) {
+    (emit_set(em, active[K] && (g[K] & kAccept), x[K], i[K], a.own_off, a.own_ids), ...);
+}
+
+template <uint32_t... K>
+__device__ __forceinline__ void emit_found(const QgArgs &a, Emitter &em, const bool (&hit)[kWalks],
+                                           const uint32_t (&own)[kWalks], const uint32_t (&x)[kWalks],
+                                           const uint32_t (&p)[kWalks], std::integer_sequence<uint32_t, K...>) {
+    (emit_set(em, hit[K] && own[K], x[K], p[K] + kQgQ - 1u, a.own_off, a.own_ids), ...);
+}
+
+// Goto walks of kWalks starts per lane from states x[k] (those with
+// active[k]), over the bytes from i[k] on: each step into a state where
+// patterns end reports them at that byte. A walk ends at the first missing
+// edge, a byte in no pattern or the end of the text. The walks of a lane
+// advance together, so their loads are in flight at once.
+__device__ __forceinline__ void walk_on(const QgArgs &a, const uint8_t *s_cmap, bool (&active)[kWalks],
+                                        uint32_t (&x)[kWalks], uint32_t (&i)[kWalks], Emitter &em) {
+    while (true) {
+        bool any = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) {
+            if (active[k] && i[k] >= a.n) active[k] = false;
+            any |= active[k];
+        }
+        if (!__any(any)) break;
+        uint32_t b[kWalks], g[kWalks];
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) b[k] = active[k] ? a.text[i[k]] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) {
+            const uint32_t c = s_cmap[b[k]];
+            g[k] = active[k] && c != a.no_class ? a.go[x[k] * a.n_cols + c] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) {
+            active[k] = g[k] != 0u;
+            if (active[k]) x[k] = g[k] & kStateMask;
+        }
+        // matches are rare: one wave-wide test before the per-walk emits (one
+        // call per walk, written out: a loop around the wave-wide emits would
+        // not be unrolled and would index the arrays at run time)
+        bool acc = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) acc |= active[k] && (g[k] & kAccept);
+        if (__any(acc)) emit_walks(a, em, active, g, x, i, std::make_integer_sequence<uint32_t, kWalks>());
+        for (uint32_t k = 0; k < kWalks; ++k) ++i[k];
+    }
+}
+
+// Look up the windows at the start positions p[k] (those with has[k];
+// p[k] + kQgQ <= n) in the table and walk on from the states of those found.
+__device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cmap, const bool (&has)[kWalks],
+                                            const uint32_t (&p)[kWalks], Emitter &em) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-    return make_uint4(x[0], x[1], x[2], x[3]);
-}
-
-// Goto walks from state x of the lanes with `active`, over the bytes from i
-// on: each step into a state where patterns end reports them at that byte.
-// A walk ends at the first missing edge, a byte in no pattern or the end of
-// the text.
-__device__ __forceinline__ void walk_on(const QgArgs &a, const uint8_t *s_cmap, bool active, uint32_t x,
-                                        uint32_t i, Emitter &em) {
-    while (__any(active)) {
-        uint32_t g = 0;
-        if (active) {
-            if (i >= a.n) {
-                active = false;
-            } else {
-                const uint32_t c = s_cmap[a.text[i]];
-                g = c != a.no_class ? a.go[x * a.n_cols + c] : 0u;
-                active = g != 0u;
-                if (active) x = g & kStateMask;
-            }
-        }
-        emit_set(em, active && (g & kAccept), x, i, a.own_off, a.own_ids);
-        ++i;
+    const uint32_t *t = reinterpret_cast<const uint32_t *>(a.text);
+    const uint32_t last = (a.n - 1u) >> 2;
+    uint32_t w[kWalks][3];
+#pragma unroll
+    for (uint32_t k = 0; k < kWalks; ++k) {
+        const uint32_t i0 = p[k] >> 2;
+#pragma unroll
+        for (uint32_t j = 0; j < 3; ++j) w[k][j] = has[k] ? t[min(i0 + j, last)] : 0u;
     }
-}
-
-// Look up the windows at the start positions p (lanes with `has`; p + kQgQ
-// <= n) in the table and walk on from the states of those found.
-__device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cmap, bool has, uint32_t p,
-                                            Emitter &em) {
-    bool hit = false;
-    uint32_t x = 0, own = 0;
-    if (has) {
-        const uint32_t *t = reinterpret_cast<const uint32_t *>(a.text);
-        const uint32_t last = (a.n - 1u) >> 2, i0 = p >> 2, sh = p & 3u;
-        const uint32_t w0 = t[i0], w1 = t[min(i0 + 1u, last)], w2 = t[min(i0 + 2u, last)];
-        // bytes p .. p + 3 and p + 4 .. p + 7 (those at or past n unused)
-        const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh);
-        const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
-        const uint32_t wx = lo & 0xffffffu, wy = (lo >> 24) | (hi & 0xffffu) << 8;
-        const uint32_t k1 = (hi & 0xffffu) | kQgUsed;
-        uint32_t slot = (mul_u24(wx, kQgK3) ^ mul_u24(wy, kQgK4)) >> a.tab_shift;
-        while (true) {
-            const uint4 e = a.tab[slot];
-            if (!(e.y & kQgUsed)) break;
-            if (e.x == lo && e.y == k1) {
-                hit = true;
-                x = e.z;
-                own = e.w;
-                break;
-            }
-            slot = (slot + 1u) & a.tab_mask;
+    // the window as the table keeps it: bytes p .. p + 3, bytes p + 4, p + 5
+    uint32_t lo[kWalks], k1[kWalks], slot[kWalks];
+    bool open[kWalks], hit[kWalks];
+#pragma unroll
+    for (uint32_t k = 0; k < kWalks; ++k) {
+        const uint32_t sh = p[k] & 3u;
+        lo[k] = __builtin_amdgcn_alignbyte(w[k][1], w[k][0], sh);
+        const uint32_t hi = __builtin_amdgcn_alignbyte(w[k][2], w[k][1], sh) & 0xffffu;
+        k1[k] = hi | kQgUsed;
+        const uint32_t wx = lo[k] & 0xffffffu, wy = (lo[k] >> 24) | hi << 8;
+        slot[k] = (mul_u24(wx, kQgK3) ^ mul_u24(wy, kQgK4)) >> a.tab_shift;
+        open[k] = has[k];
+        hit[k] = false;
+    }
+    uint32_t x[kWalks] = {}, own[kWalks] = {};
+    while (true) {
+        bool any = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) any |= open[k];
+        if (!__any(any)) break;
+        u32x4 e[kWalks];
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k)
+            e[k] = open[k] ? *reinterpret_cast<const u32x4 *>(a.tab + slot[k]) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (uint32_t k = 0; k < kWalks; ++k) {
+            // an empty slot ends the probe (not found), the window's entry ends it found
+            const bool match = open[k] && e[k].x == lo[k] && e[k].y == k1[k];
+            hit[k] |= match;
+            x[k] = match ? e[k].z : x[k];
+            own[k] = match ? e[k].w : own[k];
+            open[k] = open[k] && !match && (e[k].y & kQgUsed);
+            slot[k] = (slot[k] + 1u) & a.tab_mask;
         }
     }
-    emit_set(em, hit && own, x, p + kQgQ - 1u, a.own_off, a.own_ids);
-    walk_on(a, s_cmap, hit, x, p + kQgQ, em);
+    bool found = false;
+#pragma unroll
+    for (uint32_t k = 0; k < kWalks; ++k) found |= hit[k] && own[k];
+    if (__any(found)) emit_found(a, em, hit, own, x, p, std::make_integer_sequence<uint32_t, kWalks>());
+    uint32_t i[kWalks];
+#pragma unroll
+    for (uint32_t k = 0; k < kWalks; ++k) i[k] = p[k] + kQgQ;
+    walk_on(a, s_cmap, hit, x, i, em);
 }
 
-// Walk up to 64 of the qn starts queued at q, one per lane; returns how many
-// wait afterwards.
+// Walk up to 64 * kWalks of the qn starts queued at q, kWalks per lane;
+// returns how many wait afterwards.
 __device__ __forceinline__ uint32_t drain_starts(const QgArgs &a, const uint8_t *s_cmap, const uint32_t *q,
                                                  uint32_t qn, Emitter &em) {
     const uint32_t lane = __lane_id();
-    const uint32_t took = min(qn, 64u);
+    const uint32_t took = min(qn, 64u * kWalks);
+    bool has[kWalks];
+    uint32_t p[kWalks];
     __builtin_amdgcn_wave_barrier();
-    const uint32_t p = lane < took ? q[qn - took + lane] : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < kWalks; ++k) {
+        const uint32_t e = lane + 64u * k;
+        has[k] = e < took;
+        p[k] = has[k] ? q[qn - took + e] : 0u;
+    }
     __builtin_amdgcn_wave_barrier();
-    walk_starts(a, s_cmap, lane < took, p, em);
+    walk_starts(a, s_cmap, has, p, em);
     return qn - took;
 }
 
@@ -166,8 +231,9 @@ __device__ __forceinline__ uint32_t test_windows(const uint32_t *s_bits, const u
 // The windows of one wave step. Lane l (l >= 1) owns the 16 bytes at pos (v);
 // P2, P3 are the last 8 bytes of the lane below. `valid` masks the windows
 // (by their last byte) that lie inside the text. Passing starts are queued at
-// q (qn of them waiting, the same in every lane); whenever 63 or more wait (a
-// queue below 63 takes a round's at most 63 new ones) up to 64 are walked.
+// q (qn of them waiting, the same in every lane); whenever kDrainAt or more
+// wait, all are walked (a queue below kDrainAt takes a round's at most 63 new
+// ones, and a drain takes up to 64 * kWalks).
 __device__ __forceinline__ void step_windows(const QgArgs &a, const uint32_t *s_bits, const uint8_t *s_cmap,
                                              const uint4 &v, uint32_t P2, uint32_t P3, uint32_t pos, uint32_t valid,
                                              uint32_t *q, uint32_t &qn, Emitter &em) {
@@ -184,7 +250,7 @@ __device__ __forceinline__ void step_windows(const QgArgs &a, const uint32_t *s_
             q[qn + lane_rank(has)] = p;
         }
         qn += uint32_t(__popcll(has));
-        if (qn >= 63) qn = drain_starts(a, s_cmap, q, qn, em);
+        if (qn >= kDrainAt) qn = drain_starts(a, s_cmap, q, qn, em);
     }
 }
 
@@ -248,7 +314,7 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
         }
         step_windows(a, s_bits, s_cmap, v, P2, P3, uint32_t(base), valid, q, qn, em);
     }
-    if (qn) drain_starts(a, s_cmap, q, qn, em);
+    while (qn) qn = drain_starts(a, s_cmap, q, qn, em);
     em.flush();
 }
 
