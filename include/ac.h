@@ -189,15 +189,16 @@ enum {
     AC_TABLE_QGATE_BITS = 15, /* uint32 [2^15]: hashed gate. For the first 6 bytes
                                 b0..b5 of every pattern, X = b0 | b1 << 8 | b2 << 16,
                                 Y = b3 | b4 << 8 | b5 << 16 and
-                                h = X * 0x9E3779 ^ Y * 0x85EBCB (32-bit products),
-                                word h >> 17 has bits (h >> 12) & 31 and
-                                (h >> 7) & 31 set (empty without this gate) */
+                                h = X * 0x9E3779 + Y * 0x85EBCB (mod 2^32),
+                                word h >> 17 has bits (h >> 12) & 31 and h & 31
+                                set (empty without this gate) */
     AC_TABLE_QGATE_TAB = 16   /* uint32 [slots][4], slots a power of two: one entry
                                 per distinct 6-byte pattern start,
                                 {X | (Y & 255) << 24, Y >> 8 | 1 << 31, goto state
-                                after the 6 bytes, 1 if patterns end there}, at the
-                                first free slot from
-                                (X * 0xC2B2AF ^ Y * 0x27D4EB) >> (32 - log2 slots) on */
+                                after the 6 bytes, 1 if patterns end there}, in slot
+                                (X * 0xC2B2AF ^ Y * 0x27D4EB) >> (32 - log2 slots)
+                                or slot (X * 0x165667 ^ Y * 0xD3A2E5) >> (32 - log2
+                                slots); unused slots are zero */
 };
 
 /*

@@ -199,27 +199,60 @@ void build_qgate(Machine &m, const uint8_t *pat, const uint64_t *off) {
     wins.erase(std::unique(wins.begin(), wins.end(), [](const Win &a, const Win &b) { return a.x == b.x && a.y == b.y; }),
                wins.end());
     m.qg_bits.assign(kQgWords, 0u);
-    uint32_t bits = 8;
-    while ((1ull << bits) < 2ull * wins.size()) ++bits;
-    m.qg_tab_bits = bits;
-    m.qg_tab.assign(size_t(4) << bits, 0u);
-    const uint32_t mask = (1u << bits) - 1u;
     double cover = 0.0;
     for (const Win &w : wins) {
         const uint32_t h = qg_hash(w.x, w.y);
         m.qg_bits[qg_word(h)] |= qg_mask(h);
-        uint32_t slot = qg_slot_hash(w.x, w.y) >> (32 - bits);
-        while (m.qg_tab[size_t(slot) * 4 + 1] & kQgUsed) slot = (slot + 1) & mask;
-        uint32_t *e = &m.qg_tab[size_t(slot) * 4];
-        e[0] = w.x | (w.y & 0xffu) << 24;
-        e[1] = w.y >> 8 | kQgUsed;
-        e[2] = w.node;
-        e[3] = m.own_off[w.node + 1] > m.own_off[w.node] ? 1u : 0u;
         double pr = 1.0;
         for (uint32_t d = 0; d < 3; ++d)
             pr *= double(freq[(w.x >> (8 * d)) & 0xffu]) * double(freq[(w.y >> (8 * d)) & 0xffu]) /
                   (double(total) * double(total));
         cover += pr;
+    }
+    // the window table: cuckoo hashing with two slot choices, at most 40% full;
+    // a table where some insertion finds no place is rebuilt twice as large
+    uint32_t bits = 8;
+    while ((1ull << bits) * 2 < 5ull * wins.size()) ++bits;
+    for (;; ++bits) {
+        const uint32_t shift = 32 - bits;
+        std::vector<int32_t> at(size_t(1) << bits, -1);  // slot -> window index
+        bool ok = true;
+        for (uint32_t k = 0; k < wins.size() && ok; ++k) {
+            uint32_t cur = k;
+            uint32_t slot = qg_slot_a(wins[cur].x, wins[cur].y) >> shift;
+            for (uint32_t kick = 0;; ++kick) {
+                if (at[slot] < 0) {
+                    at[slot] = int32_t(cur);
+                    break;
+                }
+                const uint32_t alt = qg_slot_b(wins[cur].x, wins[cur].y) >> shift;
+                if (slot != alt && at[alt] < 0) {
+                    at[alt] = int32_t(cur);
+                    break;
+                }
+                if (kick == 500) {
+                    ok = false;
+                    break;
+                }
+                // take the slot and move its window to the other of its two
+                std::swap(cur, reinterpret_cast<uint32_t &>(at[slot]));
+                const uint32_t a = qg_slot_a(wins[cur].x, wins[cur].y) >> shift;
+                slot = a == slot ? qg_slot_b(wins[cur].x, wins[cur].y) >> shift : a;
+            }
+        }
+        if (!ok) continue;
+        m.qg_tab_bits = bits;
+        m.qg_tab.assign(size_t(4) << bits, 0u);
+        for (size_t s = 0; s < at.size(); ++s) {
+            if (at[s] < 0) continue;
+            const Win &w = wins[size_t(at[s])];
+            uint32_t *e = &m.qg_tab[s * 4];
+            e[0] = w.x | (w.y & 0xffu) << 24;
+            e[1] = w.y >> 8 | kQgUsed;
+            e[2] = w.node;
+            e[3] = m.own_off[w.node + 1] > m.own_off[w.node] ? 1u : 0u;
+        }
+        break;
     }
     // a window that begins no pattern passes when both of its bits are set:
     // about the mean over words of (set bits / 32)^2

@@ -50,19 +50,22 @@ inline constexpr uint32_t gate2_hash(uint32_t code24) { return (code24 * 0x9E377
 // Hashed start-position gate (machines whose patterns are all at least kQgQ
 // bytes long and that have no class gate). A window is the kQgQ bytes from a
 // start position on, read as X = bytes 0..2 and Y = bytes 3..5 (each little
-// endian, 24 bits). qg_hash(X, Y) picks a word of a 2^20-bit bitmap (bits 17
-// and up) and two bits in it (bits 12..16 and 7..11): a blocked Bloom filter
-// over the windows that begin some pattern. A table of those windows,
-// open-addressed by qg_slot_hash, gives the goto state each one leads to.
+// endian, 24 bits). qg_hash(X, Y) (32-bit arithmetic) picks a word of a 2^20-bit bitmap (bits 17
+// and up) and two bits in it (bits 12..16 and 0..4): a blocked Bloom filter
+// over the windows that begin some pattern. A table of those windows, each
+// in one of its two slots (cuckoo hashing: qg_slot_a / qg_slot_b), gives the
+// goto state each one leads to.
 constexpr uint32_t kQgQ = 6;
 constexpr uint32_t kQgWords = 1u << 15;
 constexpr uint32_t kQgK1 = 0x9E3779u, kQgK2 = 0x85EBCBu;  // odd, below 2^24
 constexpr uint32_t kQgK3 = 0xC2B2AFu, kQgK4 = 0x27D4EBu;
+constexpr uint32_t kQgK5 = 0x165667u, kQgK6 = 0xD3A2E5u;
 constexpr uint32_t kQgUsed = 0x80000000u;  // table entry word 1: slot in use
-inline constexpr uint32_t qg_hash(uint32_t x, uint32_t y) { return x * kQgK1 ^ y * kQgK2; }
-inline constexpr uint32_t qg_slot_hash(uint32_t x, uint32_t y) { return x * kQgK3 ^ y * kQgK4; }
+inline constexpr uint32_t qg_hash(uint32_t x, uint32_t y) { return x * kQgK1 + y * kQgK2; }
+inline constexpr uint32_t qg_slot_a(uint32_t x, uint32_t y) { return x * kQgK3 ^ y * kQgK4; }
+inline constexpr uint32_t qg_slot_b(uint32_t x, uint32_t y) { return x * kQgK5 ^ y * kQgK6; }
 inline constexpr uint32_t qg_word(uint32_t h) { return h >> 17; }
-inline constexpr uint32_t qg_mask(uint32_t h) { return 1u << ((h >> 12) & 31u) | 1u << ((h >> 7) & 31u); }
+inline constexpr uint32_t qg_mask(uint32_t h) { return 1u << ((h >> 12) & 31u) | 1u << (h & 31u); }
 
 struct Machine {
     uint32_t n_patterns = 0;
@@ -128,8 +131,9 @@ struct Machine {
     //   qg_tab   2^qg_tab_bits slots of 4 words, one per distinct window:
     //            {X | (Y & 0xff) << 24, Y >> 8 | kQgUsed, goto state the
     //            window leads to from the root, 1 if patterns end there};
-    //            a window's slot is the first free one from the top
-    //            qg_tab_bits bits of qg_slot_hash(X, Y) on, wrapping.
+    //            a window sits in slot qg_slot_a(X, Y) >> (32 - qg_tab_bits)
+    //            or slot qg_slot_b(X, Y) >> (32 - qg_tab_bits); unused
+    //            slots are all zero.
     std::vector<uint32_t> qg_bits, qg_tab;
     uint32_t qg_tab_bits = 0;
     // Expected fraction of start positions the gate passes: for the class

@@ -9,9 +9,10 @@
 // the first kQgQ bytes of some pattern. A blocked Bloom filter over those
 // windows, 2^20 bits in LDS, tests each start with one LDS read: two bits of
 // one word, picked by a multiplicative hash of the window. A start that
-// passes is looked up in a hash table of the windows (in global memory, small
-// enough to stay in L2), which rejects the filter's false positives and gives
-// the goto state after the window; the walk goes on from there.
+// passes is looked up in a table of the windows (in global memory, small
+// enough to stay in L2; each window in one of two slots, both read at once),
+// which rejects the filter's false positives and gives the goto state after
+// the window; the walk goes on from there.
 //
 // A wave step reads 1 KiB of text, 16 bytes per lane in one coalesced load,
 // and owns the last 1008 of them: lane 0 holds the 16 bytes before, so that
@@ -50,7 +51,6 @@ struct QgArgs {
     const uint32_t *bits;  // kQgWords words
     const uint4 *tab;      // the window table
     uint32_t tab_shift;    // 32 - log2 of its slots
-    uint32_t tab_mask;     // slots - 1
     uint32_t no_class;     // byte-map value of bytes in no pattern
     const uint32_t *go, *own_off, *own_ids;
     const uint8_t *cmap;
@@ -137,9 +137,9 @@ __device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cm
 #pragma unroll
         for (uint32_t j = 0; j < 3; ++j) w[k][j] = has[k] ? t[min(i0 + j, last)] : 0u;
     }
-    // the window as the table keeps it: bytes p .. p + 3, bytes p + 4, p + 5
-    uint32_t lo[kWalks], k1[kWalks], slot[kWalks];
-    bool open[kWalks], hit[kWalks];
+    // the window as the table keeps it (bytes p .. p + 3; bytes p + 4, p + 5)
+    // and its two slots; it is in one of them or not in the table
+    uint32_t lo[kWalks], k1[kWalks], sa[kWalks], sb[kWalks];
 #pragma unroll
     for (uint32_t k = 0; k < kWalks; ++k) {
         const uint32_t sh = p[k] & 3u;
@@ -147,30 +147,24 @@ __device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cm
         const uint32_t hi = __builtin_amdgcn_alignbyte(w[k][2], w[k][1], sh) & 0xffffu;
         k1[k] = hi | kQgUsed;
         const uint32_t wx = lo[k] & 0xffffffu, wy = (lo[k] >> 24) | hi << 8;
-        slot[k] = (mul_u24(wx, kQgK3) ^ mul_u24(wy, kQgK4)) >> a.tab_shift;
-        open[k] = has[k];
-        hit[k] = false;
+        sa[k] = (mul_u24(wx, kQgK3) ^ mul_u24(wy, kQgK4)) >> a.tab_shift;
+        sb[k] = (mul_u24(wx, kQgK5) ^ mul_u24(wy, kQgK6)) >> a.tab_shift;
     }
-    uint32_t x[kWalks] = {}, own[kWalks] = {};
-    while (true) {
-        bool any = false;
+    u32x4 ea[kWalks], eb[kWalks];
 #pragma unroll
-        for (uint32_t k = 0; k < kWalks; ++k) any |= open[k];
-        if (!__any(any)) break;
-        u32x4 e[kWalks];
+    for (uint32_t k = 0; k < kWalks; ++k) {
+        ea[k] = has[k] ? *reinterpret_cast<const u32x4 *>(a.tab + sa[k]) : u32x4{0u, 0u, 0u, 0u};
+        eb[k] = has[k] ? *reinterpret_cast<const u32x4 *>(a.tab + sb[k]) : u32x4{0u, 0u, 0u, 0u};
+    }
+    bool hit[kWalks];
+    uint32_t x[kWalks], own[kWalks];
 #pragma unroll
-        for (uint32_t k = 0; k < kWalks; ++k)
-            e[k] = open[k] ? *reinterpret_cast<const u32x4 *>(a.tab + slot[k]) : u32x4{0u, 0u, 0u, 0u};
-#pragma unroll
-        for (uint32_t k = 0; k < kWalks; ++k) {
-            // an empty slot ends the probe (not found), the window's entry ends it found
-            const bool match = open[k] && e[k].x == lo[k] && e[k].y == k1[k];
-            hit[k] |= match;
-            x[k] = match ? e[k].z : x[k];
-            own[k] = match ? e[k].w : own[k];
-            open[k] = open[k] && !match && (e[k].y & kQgUsed);
-            slot[k] = (slot[k] + 1u) & a.tab_mask;
-        }
+    for (uint32_t k = 0; k < kWalks; ++k) {
+        const bool ma = ea[k].x == lo[k] && ea[k].y == k1[k];
+        const bool mb = eb[k].x == lo[k] && eb[k].y == k1[k];
+        hit[k] = has[k] && (ma || mb);
+        x[k] = ma ? ea[k].z : eb[k].z;
+        own[k] = ma ? ea[k].w : eb[k].w;
     }
     bool found = false;
 #pragma unroll
@@ -215,11 +209,10 @@ __device__ __forceinline__ uint32_t bytes_at(const uint32_t (&r)[6]) {
 template <int J>
 __device__ __forceinline__ uint32_t test_window(const uint32_t *s_bits, const uint32_t (&r)[6]) {
     // the window ending at byte J: X = bytes J-5 .. J-3, Y = bytes J-2 .. J
-    const uint32_t h = mul_u24(bytes_at<J - 5>(r), kQgK1) ^ mul_u24(bytes_at<J - 2>(r), kQgK2);
+    const uint32_t h = mul_u24(bytes_at<J - 5>(r), kQgK1) + mul_u24(bytes_at<J - 2>(r), kQgK2);
     const uint32_t word = s_bits[h >> 17];
-    // bits (h >> 12) mod 32 and (h >> 7) mod 32 (the field offsets take the
-    // low 5 bits)
-    return (__builtin_amdgcn_ubfe(word, h >> 12, 1u) & __builtin_amdgcn_ubfe(word, h >> 7, 1u)) << J;
+    // bits (h >> 12) mod 32 and h mod 32 (the field offsets take the low 5 bits)
+    return (__builtin_amdgcn_ubfe(word, h >> 12, 1u) & __builtin_amdgcn_ubfe(word, h, 1u)) << J;
 }
 
 template <int... J>
@@ -341,7 +334,6 @@ int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, 
     a.bits = dm.qg_bits;
     a.tab = reinterpret_cast<const uint4 *>(dm.qg_tab);
     a.tab_shift = 32u - dm.qg_tab_bits;
-    a.tab_mask = (1u << dm.qg_tab_bits) - 1u;
     a.go = dm.go;
     a.own_off = dm.own_off;
     a.own_ids = dm.own_ids;
