@@ -35,13 +35,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_steps(fn, steps, stream, torch):
-    """Per-step HIP event pairs on `stream` (the stream the kernels run on)."""
+def time_steps(fn, steps, stream, torch, pre=None):
+    """Per-step HIP event pairs on `stream` (the stream the kernels run on);
+    pre(i), when given, runs in each step before its first event."""
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
+        if pre is not None:
+            pre(i)
         evs[i][0].record(stream)
         fn(i)
         evs[i][1].record(stream)
@@ -58,6 +61,9 @@ PROFILES = {
                                     "paper_1403_1305_amd/csrc/dfa.hip"]),
     "gated": ("gate_scan_dna256m.md", ["paper_1403_1305_amd/csrc/gate.hip",
                                        "paper_1403_1305_amd/csrc/device_common.h"]),
+    "qgated": ("qgate_scan_protein1g.md", ["paper_1403_1305_amd/csrc/qgate.hip",
+                                           "paper_1403_1305_amd/csrc/device_common.h",
+                                           "paper_1403_1305_amd/csrc/machine.h"]),
 }
 ALGOS = {"auto": 0, "dfa": 1, "pfac": 2, "gated": 3}
 ALGO_NAMES = {1: "dfa", 2: "pfac", 3: "gated"}
@@ -77,14 +83,14 @@ def profiled_traffic(workload, kind):
     or None when the summary is for another workload or the kernel sources
     have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", PROFILES[kind][0]) if kind in PROFILES else ""
-    if workload != "dna256m" or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith(("|", "#", " ")):
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != kernel_source_sha256(kind):
+    if fields.get("workload") != workload or fields.get("kernel_source_sha256") != kernel_source_sha256(kind):
         return None
     return int(fields["traffic_bytes_per_launch"])
 
@@ -501,18 +507,26 @@ def main():
     count = torch.zeros(1, dtype=torch.int64, device="cuda")
     algo = resolved_algo(ac, auto, ALGOS[args.algo])
     kind = ALGO_NAMES[algo]
-    opts = ac._scan_opts(algo, args.chunk, 0, args.placement, args.walkers)
+    if kind == "gated" and info["has_gate"] == 2:
+        kind = "qgated"  # the hashed gate's kernel
+    # append mode: the count is zeroed before each step's first event, so
+    # the events bracket the scan kernel alone (the launch rocprofv3 times)
+    opts = ac._scan_opts(algo, args.chunk, 0, args.placement, args.walkers, append=1)
     log("headline matcher", kind)
+
+    def zero(i):
+        count.zero_()
 
     def step(i):
         t = copies[i % 3]
         ac.ac_scan(auto, t, n, outs, cap, count, opts, stream)
 
     for i in range(args.warmup):
+        zero(i)
         step(i)
     torch.cuda.synchronize()
     log("timed", kind)
-    wall, ms = time_steps(step, args.steps, stream, torch)
+    wall, ms = time_steps(step, args.steps, stream, torch, pre=zero)
     matches = int(count.item())
     # the timed list against the oracle's digest of this workload
     golden_ok = None
@@ -543,24 +557,26 @@ def main():
     # the chunked full-DFA walk over the same text, when it is not the headline
     dfa = None
     if kind != "dfa" and not args.no_dfa:
-        dopts = ac._scan_opts(ac.AC_ALGO_DFA, args.chunk, 0, args.placement, args.walkers)
+        dopts = ac._scan_opts(ac.AC_ALGO_DFA, args.chunk, 0, args.placement, args.walkers, append=1)
         dstep = lambda i: ac.ac_scan(auto, copies[i % 3], n, outs, cap, count, dopts, stream)
         for i in range(2):
+            zero(i)
             dstep(i)
         log("timed dfa")
-        dwall, dms = time_steps(dstep, max(5, args.steps // 2), stream, torch)
+        dwall, dms = time_steps(dstep, max(5, args.steps // 2), stream, torch, pre=zero)
         dfa = {"value": round(n * len(dms) / dwall / 1e9, 3), "unit": "GB/s",
                "kernel_ms": round(float(np.mean(dms)), 4), "kernel_ms_median": round(float(np.median(dms)), 4),
                "matches": int(count.item()), "traffic": profiled_traffic(args.workload, "dfa")}
 
     pfac = None
     if not args.no_pfac:
-        popts = ac._scan_opts(ac.AC_ALGO_PFAC, 0, 0, 0)
+        popts = ac._scan_opts(ac.AC_ALGO_PFAC, 0, 0, 0, append=1)
         pstep = lambda i: ac.ac_scan(auto, copies[i % 3], n, outs, cap, count, popts, stream)
         for i in range(2):
+            zero(i)
             pstep(i)
         log("timed pfac")
-        pwall, pms = time_steps(pstep, max(3, args.steps // 4), stream, torch)
+        pwall, pms = time_steps(pstep, max(3, args.steps // 4), stream, torch, pre=zero)
         pfac = {"value": round(n * len(pms) / pwall / 1e9, 3), "unit": "GB/s",
                 "kernel_ms": round(float(np.mean(pms)), 4), "matches": int(count.item())}
 
@@ -581,9 +597,10 @@ def main():
         d0, o0 = ac.patterns_csr(w0.patterns)
         a0 = ac.ac_build(d0, o0)
         for i in range(2):
+            zero(i)
             ac.ac_scan(a0, copies[i % 3], n, outs, cap, count, opts, stream)
         _, ms0 = time_steps(lambda i: ac.ac_scan(a0, copies[i % 3], n, outs, cap, count, opts, stream),
-                            10, stream, torch)
+                            10, stream, torch, pre=zero)
         e1 = {"planted": 0.0, "kernel_ms_median": round(float(np.median(ms0)), 4),
               "matches": int(count.item()), "planted_10pct_kernel_ms_median": round(kernel_ms_median, 4),
               "ratio": round(float(np.median(ms0)) / kernel_ms_median, 3)}
@@ -595,16 +612,17 @@ def main():
         others = [other, other.clone(), other.clone()]
         del other
         for i in range(2):
+            zero(i)
             ac.ac_scan(auto, others[i % 3], n, outs, cap, count, opts, stream)
         _, ms1 = time_steps(lambda i: ac.ac_scan(auto, others[i % 3], n, outs, cap, count, opts, stream),
-                            10, stream, torch)
+                            10, stream, torch, pre=zero)
         e1["same_machine_unrelated_text"] = {
             "kernel_ms_median": round(float(np.median(ms1)), 4), "matches": int(count.item()),
             "ratio": round(float(np.median(ms1)) / kernel_ms_median, 3)}
         del others
         # the timed text again, after the two runs above (drift of the device's clocks)
         _, ms2 = time_steps(lambda i: ac.ac_scan(auto, copies[i % 3], n, outs, cap, count, opts, stream),
-                            10, stream, torch)
+                            10, stream, torch, pre=zero)
         e1["timed_text_again_kernel_ms_median"] = round(float(np.median(ms2)), 4)
 
     if args.calib_copy:

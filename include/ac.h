@@ -232,6 +232,9 @@ typedef struct {
                              looks up two bytes at once when the automaton was
                              built with AC_BUILD_PAIR_ROWS (ac_info_t.pair_states
                              > 0); AC_PAIR_OFF = one byte per lookup */
+    uint32_t append;      /* 0 = *d_count is reset first; 1 = it is kept and the new
+                             matches go after the ones it counts (several scans
+                             then fill one list, and no reset runs on the stream) */
 } ac_scan_opts;
 
 enum { AC_PAIR_AUTO = 0, AC_PAIR_OFF = 1 };

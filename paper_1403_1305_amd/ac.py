@@ -76,7 +76,7 @@ class ac_scan_opts(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("block", ctypes.c_uint32), ("placement", ctypes.c_uint32),
                 ("walkers", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32),
-                ("pair_steps", ctypes.c_uint32)]
+                ("pair_steps", ctypes.c_uint32), ("append", ctypes.c_uint32)]
 
 
 class ac_batch_tune(ctypes.Structure):
@@ -274,8 +274,8 @@ def ac_get_table(a: Automaton, which: int) -> np.ndarray:
     return out[: size.value // np.dtype(dt).itemsize]
 
 
-def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0, walkers=0, block_bytes=0, pair_steps=0):
-    return ac_scan_opts(algo, chunk, block, placement, walkers, block_bytes, pair_steps)
+def _scan_opts(algo=AC_ALGO_DFA, chunk=0, block=0, placement=0, walkers=0, block_bytes=0, pair_steps=0, append=0):
+    return ac_scan_opts(algo, chunk, block, placement, walkers, block_bytes, pair_steps, append)
 
 
 def ac_scan(a: Automaton, d_text, n: int, d_matches, capacity: int, d_count,

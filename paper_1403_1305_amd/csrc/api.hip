@@ -283,6 +283,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         return fail(AC_ERR_INVALID, "ac_scan: text must be 16-byte aligned");
     acm::ScanConfig cfg;
     uint32_t want = AC_PLACE_AUTO;
+    bool append = false;
     if (opts) {
         cfg.algo = opts->algo;
         cfg.chunk = opts->chunk;
@@ -292,6 +293,8 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
         cfg.pair_steps = opts->pair_steps == AC_PAIR_AUTO;
         want = opts->placement;
         if (opts->pair_steps > AC_PAIR_OFF) return fail(AC_ERR_INVALID, "ac_scan: unknown pair_steps");
+        if (opts->append > 1) return fail(AC_ERR_INVALID, "ac_scan: append must be 0 or 1");
+        append = opts->append != 0;
     }
     if (cfg.algo > AC_ALGO_GATED) return fail(AC_ERR_INVALID, "ac_scan: unknown algo");
     if (cfg.algo == AC_ALGO_AUTO) cfg.algo = acm::auto_algo(a);
@@ -305,7 +308,7 @@ int ac_scan(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *
     if (hipGetDevice(&dev) != hipSuccess || dev != a->device) return fail(AC_ERR_INVALID, "ac_scan: automaton lives on another device");
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::string err;
-    int rc = acm::launch_zero_count(d_count, s, err);
+    int rc = append ? AC_OK : acm::launch_zero_count(d_count, s, err);
     if (rc == AC_OK) {
         if (cfg.algo == AC_ALGO_DFA)
             rc = acm::launch_dfa_scan(a->dm, d_text, n, d_matches, capacity, d_count, cfg, s, err);
@@ -344,6 +347,8 @@ int ac_scan_stream(const ac_automaton *a, const uint8_t *d_text, uint64_t n, uin
         cfg.pair_steps = opts->pair_steps == AC_PAIR_AUTO;
         want = opts->placement;
         if (opts->pair_steps > AC_PAIR_OFF) return fail(AC_ERR_INVALID, "ac_scan_stream: unknown pair_steps");
+        if (opts->append > 1) return fail(AC_ERR_INVALID, "ac_scan_stream: append must be 0 or 1");
+        append = append || opts->append;
     }
     if (!resolve_placement(a, want, cfg.placement))
         return fail(AC_ERR_INVALID, "ac_scan_stream: placement not available for this automaton");

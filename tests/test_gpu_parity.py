@@ -421,3 +421,32 @@ def test_scan_captured_in_a_graph(small):
         assert np.array_equal(np.sort(ac.keys_to_numpy(out[:expect.size])), expect), i
         ac.scan_text(a, other)  # eager work between replays
         torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- append mode
+
+@pytest.mark.parametrize("algo,alphabet", [(ac.AC_ALGO_DFA, "dna"), (ac.AC_ALGO_PFAC, "dna"),
+                                           (ac.AC_ALGO_GATED, "dna"), (ac.AC_ALGO_GATED, "protein")])
+def test_append_mode_fills_one_list(algo, alphabet):
+    """With append set, *d_count is kept: two scans of two texts leave both
+    lists, one after the other, and the sum of their counts."""
+    name = "dna1m" if alphabet == "dna" else "protein1g"
+    w = plain_workload(name, n=1 << 20)
+    pats = [p for p in w.patterns if len(p) >= 6][:2000]
+    a = build(pats)
+    t1, t2 = w.text[: 300_000], w.text[300_000: 700_017]
+    e1, e2 = oracle.oracle_match(t1, pats), oracle.oracle_match(t2, pats)
+    out = torch.full((e1.size + e2.size + 64,), -1, dtype=torch.int64, device="cuda")
+    cnt = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    opts = ac._scan_opts(algo, append=1)
+    cnt.zero_()
+    ac.ac_scan(a, to_device(t1), t1.size, out, out.numel(), cnt, opts)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == e1.size
+    ac.ac_scan(a, to_device(t2), t2.size, out, out.numel(), cnt, opts)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == e1.size + e2.size
+    got = ac.keys_to_numpy(out[: e1.size + e2.size])
+    assert np.array_equal(np.sort(got), np.sort(np.concatenate([e1, e2])))
+    with pytest.raises(ac.AcError):
+        ac.ac_scan(a, to_device(t1), t1.size, out, out.numel(), cnt, ac._scan_opts(algo, append=2))
