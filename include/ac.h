@@ -194,8 +194,10 @@ enum {
                                 set (empty without this gate) */
     AC_TABLE_QGATE_TAB = 16   /* uint32 [slots][4], slots a power of two: one entry
                                 per distinct 6-byte pattern start,
-                                {X | (Y & 255) << 24, Y >> 8 | 1 << 31, goto state
-                                after the 6 bytes, 1 if patterns end there}, in slot
+                                {X | (Y & 255) << 24, Y >> 8 | 1 << 31 | 1 << 30 if
+                                patterns end at the goto state after the 6 bytes,
+                                that state, its children (bit c set for an edge of
+                                class c; all bits beyond 32 classes)}, in slot
                                 (X * 0xC2B2AF ^ Y * 0x27D4EB) >> (32 - log2 slots)
                                 or slot (X * 0x165667 ^ Y * 0xD3A2E5) >> (32 - log2
                                 slots); unused slots are zero */

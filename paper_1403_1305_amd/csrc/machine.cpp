@@ -248,9 +248,12 @@ void build_qgate(Machine &m, const uint8_t *pat, const uint64_t *off) {
             const Win &w = wins[size_t(at[s])];
             uint32_t *e = &m.qg_tab[s * 4];
             e[0] = w.x | (w.y & 0xffu) << 24;
-            e[1] = w.y >> 8 | kQgUsed;
+            e[1] = w.y >> 8 | kQgUsed | (m.own_off[w.node + 1] > m.own_off[w.node] ? kQgOwn : 0u);
             e[2] = w.node;
-            e[3] = m.own_off[w.node + 1] > m.own_off[w.node] ? 1u : 0u;
+            uint32_t kids = C > 32 ? ~0u : 0u;
+            for (uint32_t c = 0; c < C && C <= 32; ++c)
+                if (m.go[size_t(w.node) * C + c]) kids |= 1u << c;
+            e[3] = kids;
         }
         break;
     }

@@ -61,6 +61,7 @@ constexpr uint32_t kQgK1 = 0x9E3779u, kQgK2 = 0x85EBCBu;  // odd, below 2^24
 constexpr uint32_t kQgK3 = 0xC2B2AFu, kQgK4 = 0x27D4EBu;
 constexpr uint32_t kQgK5 = 0x165667u, kQgK6 = 0xD3A2E5u;
 constexpr uint32_t kQgUsed = 0x80000000u;  // table entry word 1: slot in use
+constexpr uint32_t kQgOwn = 0x40000000u;   // table entry word 1: patterns end at the state
 inline constexpr uint32_t qg_hash(uint32_t x, uint32_t y) { return x * kQgK1 + y * kQgK2; }
 inline constexpr uint32_t qg_slot_a(uint32_t x, uint32_t y) { return x * kQgK3 ^ y * kQgK4; }
 inline constexpr uint32_t qg_slot_b(uint32_t x, uint32_t y) { return x * kQgK5 ^ y * kQgK6; }
@@ -129,8 +130,11 @@ struct Machine {
     //            (X, Y) of every pattern's first kQgQ bytes, both bits of
     //            qg_mask(h) are set in word qg_word(h), h = qg_hash(X, Y);
     //   qg_tab   2^qg_tab_bits slots of 4 words, one per distinct window:
-    //            {X | (Y & 0xff) << 24, Y >> 8 | kQgUsed, goto state the
-    //            window leads to from the root, 1 if patterns end there};
+    //            {X | (Y & 0xff) << 24, Y >> 8 | kQgUsed | kQgOwn if
+    //            patterns end at the state, the goto state the window leads
+    //            to from the root, its children: bit c set when it has an
+    //            edge of class c (all bits when the machine has more than 32
+    //            classes)};
     //            a window sits in slot qg_slot_a(X, Y) >> (32 - qg_tab_bits)
     //            or slot qg_slot_b(X, Y) >> (32 - qg_tab_bits); unused
     //            slots are all zero.

@@ -37,10 +37,11 @@ constexpr uint32_t kQgWaves = kQgBlock / 64;
 constexpr uint32_t kLaneBytes = 16;
 constexpr uint32_t kOwnBytes = 63 * kLaneBytes;  // text a wave step owns
 constexpr uint32_t kPrefetch = 4;                // wave steps loaded ahead
-constexpr uint32_t kWalks = 4;                   // queued starts a lane walks at once
-constexpr uint32_t kDrainAt = 64 * kWalks - 63;  // queue length that triggers a drain
-constexpr uint32_t kStartQueue = 64 * kWalks;    // queued start positions per wave (at most kDrainAt - 1 + 63)
-constexpr uint32_t kQgLds = kQgWords * 4 + 256 + kQgWaves * (kStartQueue * 4 + kQueueBytesPerWave);
+constexpr uint32_t kWalks = 2;                   // queued starts a lane walks at once
+constexpr uint32_t kStartQueue = 125;            // queued starts per wave (position and window, 12 bytes)
+constexpr uint32_t kDrainAt = kStartQueue - 63;  // queue length that triggers a drain
+static_assert(kStartQueue <= 64 * kWalks, "a drain takes the whole queue");
+constexpr uint32_t kQgLds = kQgWords * 4 + 256 + kQgWaves * (kStartQueue * 12 + kQueueBytesPerWave);
 static_assert(kQgLds <= kLdsPerWorkgroup, "hashed gate kernel LDS");
 static_assert(kQgQ == 6, "the window extraction below assumes 6-byte windows");
 
@@ -123,30 +124,19 @@ __device__ __forceinline__ void walk_on(const QgArgs &a, const uint8_t *s_cmap, 
     }
 }
 
-// Look up the windows at the start positions p[k] (those with has[k];
-// p[k] + kQgQ <= n) in the table and walk on from the states of those found.
+// Look up the windows (bytes p .. p + 3 in lo, p + 4 and p + 5 in hi) at the
+// start positions p[k] (those with has[k]; p[k] + kQgQ <= n) in the table
+// and walk on from the states of those found.
 __device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cmap, const bool (&has)[kWalks],
-                                            const uint32_t (&p)[kWalks], Emitter &em) {
+                                            const uint32_t (&p)[kWalks], const uint32_t (&lo)[kWalks],
+                                            const uint32_t (&hi)[kWalks], Emitter &em) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    const uint32_t *t = reinterpret_cast<const uint32_t *>(a.text);
-    const uint32_t last = (a.n - 1u) >> 2;
-    uint32_t w[kWalks][3];
+    // the window's two slots; it is in one of them or not in the table
+    uint32_t k1[kWalks], sa[kWalks], sb[kWalks];
 #pragma unroll
     for (uint32_t k = 0; k < kWalks; ++k) {
-        const uint32_t i0 = p[k] >> 2;
-#pragma unroll
-        for (uint32_t j = 0; j < 3; ++j) w[k][j] = has[k] ? t[min(i0 + j, last)] : 0u;
-    }
-    // the window as the table keeps it (bytes p .. p + 3; bytes p + 4, p + 5)
-    // and its two slots; it is in one of them or not in the table
-    uint32_t lo[kWalks], k1[kWalks], sa[kWalks], sb[kWalks];
-#pragma unroll
-    for (uint32_t k = 0; k < kWalks; ++k) {
-        const uint32_t sh = p[k] & 3u;
-        lo[k] = __builtin_amdgcn_alignbyte(w[k][1], w[k][0], sh);
-        const uint32_t hi = __builtin_amdgcn_alignbyte(w[k][2], w[k][1], sh) & 0xffffu;
-        k1[k] = hi | kQgUsed;
-        const uint32_t wx = lo[k] & 0xffffffu, wy = (lo[k] >> 24) | hi << 8;
+        k1[k] = hi[k] | kQgUsed;
+        const uint32_t wx = lo[k] & 0xffffffu, wy = (lo[k] >> 24) | hi[k] << 8;
         sa[k] = (mul_u24(wx, kQgK3) ^ mul_u24(wy, kQgK4)) >> a.tab_shift;
         sb[k] = (mul_u24(wx, kQgK5) ^ mul_u24(wy, kQgK6)) >> a.tab_shift;
     }
@@ -156,15 +146,21 @@ __device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cm
         ea[k] = has[k] ? *reinterpret_cast<const u32x4 *>(a.tab + sa[k]) : u32x4{0u, 0u, 0u, 0u};
         eb[k] = has[k] ? *reinterpret_cast<const u32x4 *>(a.tab + sb[k]) : u32x4{0u, 0u, 0u, 0u};
     }
-    bool hit[kWalks];
+    bool hit[kWalks], go_on[kWalks];
     uint32_t x[kWalks], own[kWalks];
 #pragma unroll
     for (uint32_t k = 0; k < kWalks; ++k) {
-        const bool ma = ea[k].x == lo[k] && ea[k].y == k1[k];
-        const bool mb = eb[k].x == lo[k] && eb[k].y == k1[k];
+        const bool ma = ea[k].x == lo[k] && (ea[k].y & ~kQgOwn) == k1[k];
+        const bool mb = eb[k].x == lo[k] && (eb[k].y & ~kQgOwn) == k1[k];
         hit[k] = has[k] && (ma || mb);
         x[k] = ma ? ea[k].z : eb[k].z;
-        own[k] = ma ? ea[k].w : eb[k].w;
+        own[k] = (ma ? ea[k].y : eb[k].y) & kQgOwn;
+        // the walk goes on only if the next byte's class is one of the
+        // state's children (most walks end here without a goto lookup)
+        const uint32_t kids = ma ? ea[k].w : eb[k].w;
+        const uint32_t nx = p[k] + kQgQ;
+        const uint32_t c = hit[k] && nx < a.n ? s_cmap[a.text[nx]] : a.no_class;
+        go_on[k] = hit[k] && c != a.no_class && ((kids >> (c & 31u)) & 1u);
     }
     bool found = false;
 #pragma unroll
@@ -173,26 +169,34 @@ __device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cm
     uint32_t i[kWalks];
 #pragma unroll
     for (uint32_t k = 0; k < kWalks; ++k) i[k] = p[k] + kQgQ;
-    walk_on(a, s_cmap, hit, x, i, em);
+    walk_on(a, s_cmap, go_on, x, i, em);
 }
 
-// Walk up to 64 * kWalks of the qn starts queued at q, kWalks per lane;
+// The per-wave queue of passing starts: position, window bytes 0..3, window
+// bytes 4..5 (three LDS arrays).
+struct StartQueue {
+    uint32_t *p, *lo, *hi;
+};
+
+// Walk the qn starts queued at q (at most 64 * kWalks), kWalks per lane;
 // returns how many wait afterwards.
-__device__ __forceinline__ uint32_t drain_starts(const QgArgs &a, const uint8_t *s_cmap, const uint32_t *q,
+__device__ __forceinline__ uint32_t drain_starts(const QgArgs &a, const uint8_t *s_cmap, const StartQueue &q,
                                                  uint32_t qn, Emitter &em) {
     const uint32_t lane = __lane_id();
     const uint32_t took = min(qn, 64u * kWalks);
     bool has[kWalks];
-    uint32_t p[kWalks];
+    uint32_t p[kWalks], lo[kWalks], hi[kWalks];
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (uint32_t k = 0; k < kWalks; ++k) {
-        const uint32_t e = lane + 64u * k;
-        has[k] = e < took;
-        p[k] = has[k] ? q[qn - took + e] : 0u;
+        const uint32_t e = qn - took + lane + 64u * k;
+        has[k] = lane + 64u * k < took;
+        p[k] = has[k] ? q.p[e] : 0u;
+        lo[k] = has[k] ? q.lo[e] : 0u;
+        hi[k] = has[k] ? q.hi[e] : 0u;
     }
     __builtin_amdgcn_wave_barrier();
-    walk_starts(a, s_cmap, has, p, em);
+    walk_starts(a, s_cmap, has, p, lo, hi, em);
     return qn - took;
 }
 
@@ -229,18 +233,27 @@ __device__ __forceinline__ uint32_t test_windows(const uint32_t *s_bits, const u
 // ones, and a drain takes up to 64 * kWalks).
 __device__ __forceinline__ void step_windows(const QgArgs &a, const uint32_t *s_bits, const uint8_t *s_cmap,
                                              const uint4 &v, uint32_t P2, uint32_t P3, uint32_t pos, uint32_t valid,
-                                             uint32_t *q, uint32_t &qn, Emitter &em) {
+                                             const StartQueue &q, uint32_t &qn, Emitter &em) {
     const uint32_t r[6] = {P2, P3, v.x, v.y, v.z, v.w};
     uint32_t m = test_windows(s_bits, r, std::make_integer_sequence<int, 16>()) & valid;
     while (true) {
         const uint64_t has = __ballot(m != 0);
         if (has == 0) break;
-        uint32_t p = 0;
         if (m) {
             const uint32_t j = uint32_t(__builtin_ctz(m));
             m &= m - 1u;
-            p = pos + j - (kQgQ - 1u);
-            q[qn + lane_rank(has)] = p;
+            // the window's first byte is byte j + 3 of r: words g .. g + 2
+            // (g = (j + 3) / 4 in 0..4), picked by the bits of g in three
+            // stages of selects; for g = 4 the third word is not needed
+            const uint32_t g = (j + 3u) >> 2, sh = (j + 3u) & 3u;
+            const bool g4 = g >= 4u, g2 = (g & 2u) != 0u, g1 = (g & 1u) != 0u;
+            const uint32_t t0 = g4 ? r[4] : r[0], t1 = g4 ? r[5] : r[1];
+            const uint32_t u0 = g2 ? r[2] : t0, u1 = g2 ? r[3] : t1, u2 = g2 ? r[4] : r[2], u3 = g2 ? r[5] : r[3];
+            const uint32_t w0 = g1 ? u1 : u0, w1 = g1 ? u2 : u1, w2 = g1 ? u3 : u2;
+            const uint32_t e = qn + lane_rank(has);
+            q.p[e] = pos + j - (kQgQ - 1u);
+            q.lo[e] = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            q.hi[e] = __builtin_amdgcn_alignbyte(w2, w1, sh) & 0xffffu;
         }
         qn += uint32_t(__popcll(has));
         if (qn >= kDrainAt) qn = drain_starts(a, s_cmap, q, qn, em);
@@ -251,7 +264,7 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
     // static LDS: the bitmap's address is then a constant the lookups fold in
     __shared__ __align__(16) uint32_t s_bits[kQgWords];
     __shared__ __align__(16) uint8_t s_cmap[256];
-    __shared__ __align__(16) uint32_t s_queue[kQgWaves * kStartQueue];
+    __shared__ __align__(16) uint32_t s_queue[kQgWaves * kStartQueue * 3];
     __shared__ __align__(16) uint8_t s_emit[kQgWaves * kQueueBytesPerWave];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x & 63u;
     Emitter em;
@@ -263,7 +276,8 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
         if (threadIdx.x < 256) s_cmap[threadIdx.x] = a.cmap[threadIdx.x];
     }
     __syncthreads();
-    uint32_t *q = s_queue + wave * kStartQueue;
+    const StartQueue q{s_queue + wave * kStartQueue * 3, s_queue + wave * kStartQueue * 3 + kStartQueue,
+                       s_queue + wave * kStartQueue * 3 + 2 * kStartQueue};
     uint32_t qn = 0;  // queued starts (the same in every lane)
 
     const uint32_t W = gridDim.x * kQgWaves, gw = blockIdx.x * kQgWaves + wave;

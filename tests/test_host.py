@@ -458,14 +458,17 @@ def test_hashed_gate_tables_match_their_definition(seed):
         sa = (((x * 0xC2B2AF) & M) ^ ((y * 0x27D4EB) & M)) >> (32 - log2)
         sb = (((x * 0x165667) & M) ^ ((y * 0xD3A2E5) & M)) >> (32 - log2)
         key = [x | (y & 255) << 24, (y >> 8) | 1 << 31]
-        e = [tab[c] for c in (sa, sb) if [int(tab[c][0]), int(tab[c][1])] == key]
+        e = [tab[c] for c in (sa, sb) if [int(tab[c][0]), int(tab[c][1]) & ~(1 << 30)] == key]
         assert len(e) == 1 or (sa == sb and len(e) == 2), p
         e = e[0]
-        assert int(e[2]) == s and int(e[3]) == int(t.own_off[s + 1] > t.own_off[s]), p
+        assert int(e[2]) == s and (int(e[1]) >> 30) & 1 == int(t.own_off[s + 1] > t.own_off[s]), p
+        kids = sum(1 << c for c in range(t.C) if t.go[s, c]) if t.C <= 32 else 0xFFFFFFFF
+        assert int(e[3]) == kids, p
     used = tab[(tab[:, 1] >> 31) == 1]
     assert len(used) == len(windows) and 5 * len(windows) <= 2 * slots
     assert not tab[(tab[:, 1] >> 31) == 0].any()
     for e in used:
+        assert int(e[1]) & 0x3FFF0000 == 0
         key = (int(e[0]) & 0xFFFFFF, int(e[0]) >> 24 | (int(e[1]) & 0xFFFF) << 8)
         assert windows[key] == int(e[2])
     # random windows with the patterns' byte frequencies: pass rate near gate_pass
