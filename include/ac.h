@@ -442,7 +442,10 @@ int ac_scan_batch_noalloc(const ac_automaton *const *autos, uint32_t n_autos, co
  * A request loop over resident automata with continuous batching: requests
  * are admitted while others are on the device, as slots (one HIP stream
  * each) and a device-memory budget allow, and their scans overlap on the
- * GPU. A request's work runs on its slot's stream alone. Automata the gated
+ * GPU. A request's work runs on its slot's stream alone; streams that share
+ * a hardware queue run their kernels in turn, so the process should have at
+ * least as many hardware queues as slots (HIP reads GPU_MAX_HW_QUEUES at
+ * start-up; its default is 4). Automata the gated
  * scan suits (AC_ALGO_AUTO's rule) scan a request in one gated launch; the
  * others in pieces with the DFA state carried on the device from one piece to
  * the next (the per-buffer search of the paper's Alg. 1). Either way a

@@ -96,6 +96,33 @@ __device__ __forceinline__ void emit_set(Emitter &em, bool has, uint32_t s, uint
     }
 }
 
+// A launch that reports its own completion (the served form): the last
+// workgroup to finish writes the match total and the run's sequence number to
+// a completion word in host memory (total, then the sequence with release
+// order at system scope) and clears the count and the finish counter for the
+// next launch on the same stream. finished == NULL: no completion word.
+struct Completion {
+    unsigned int *finished;  // device: workgroups done so far (0 before the launch)
+    uint64_t *word;          // host-visible: {total, sequence}
+    uint64_t seq;
+};
+
+// Called by every thread of every workgroup at the end of the kernel, after
+// its last match is written.
+__device__ __forceinline__ void complete_launch(const Completion &c, unsigned long long *count) {
+    if (!c.finished) return;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    __threadfence();  // this workgroup's matches and count updates first
+    if (atomicAdd(c.finished, 1u) != gridDim.x - 1) return;
+    __threadfence();  // every other workgroup's, seen through the counter
+    const uint64_t total = __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(c.finished, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(c.word, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(c.word + 1, c.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 inline int hip_fail(hipError_t e, const char *what, std::string &err) {
     err = std::string(what) + ": " + hipGetErrorString(e);
     return AC_ERR_HIP;

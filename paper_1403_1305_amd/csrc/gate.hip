@@ -51,6 +51,7 @@ struct GateArgs {
     uint64_t *out;
     uint64_t cap;
     unsigned long long *count;
+    Completion done;
 };
 
 // Classes of 16 bytes, byte i in bits 2i and 2i+1. A dot product with the
@@ -287,12 +288,13 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
         walk_on(a, from + lane < a.n, 0u, from + lane, em);
     }
     em.flush();
+    complete_launch(a.done, a.count);
 }
 
 }  // namespace
 
 int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err) {
+                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err, const Completion *done) {
     if (!dm.gate_bits) {
         err = "ac_scan: this automaton has no start-position gate";
         return AC_ERR_INVALID;
@@ -322,6 +324,7 @@ int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     a.out = out;
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long *>(count);
+    a.done = done ? *done : Completion{nullptr, nullptr, 0};
     return launch_kernel(gate_kernel, grid, kGateBlock, 0u, stream, a, err);
 }
 

@@ -58,6 +58,7 @@ struct QgArgs {
     uint64_t *out;
     uint64_t cap;
     unsigned long long *count;
+    Completion done;
 };
 
 // Low 32 bits of the product of the low 24 bits of a and b (one full-rate
@@ -323,12 +324,13 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
     }
     while (qn) qn = drain_starts(a, s_cmap, q, qn, em);
     em.flush();
+    complete_launch(a.done, a.count);
 }
 
 }  // namespace
 
 int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err) {
+                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err, const Completion *done) {
     if (!dm.qg_bits) {
         err = "ac_scan: this automaton has no hashed start-position gate";
         return AC_ERR_INVALID;
@@ -356,6 +358,7 @@ int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, 
     a.out = out;
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long *>(count);
+    a.done = done ? *done : Completion{nullptr, nullptr, 0};
     // one workgroup per CU (the bitmap fills most of the LDS), fewer for short texts
     const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
     const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kQgWaves - 1) / kQgWaves, cus)));

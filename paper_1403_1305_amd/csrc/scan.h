@@ -73,18 +73,27 @@ int launch_dfa_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, ui
 int launch_copy_state(const uint32_t *in, uint32_t *out, hipStream_t stream, std::string &err);
 // Failure-less walks from the start positions the gate passes (dm.gate_bits
 // must be set).
+struct Completion;
+// With `done` (n > 0) the launch reports its own completion (device_common.h).
 int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err);
+                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err,
+                     const Completion *done = nullptr);
 // Failure-less walks from the start positions the hashed gate passes
 // (dm.qg_bits must be set).
+// With `done` (n >= 6) the launch reports its own completion.
 int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err);
+                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err,
+                      const Completion *done = nullptr);
 // The gated scan with whichever gate the machine has.
 inline int launch_gated_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                             uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err) {
-    return dm.gate_bits ? launch_gate_scan(dm, text, n, out, cap, count, stream, err)
-                        : launch_qgate_scan(dm, text, n, out, cap, count, stream, err);
+                             uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err,
+                             const Completion *done = nullptr) {
+    return dm.gate_bits ? launch_gate_scan(dm, text, n, out, cap, count, stream, err, done)
+                        : launch_qgate_scan(dm, text, n, out, cap, count, stream, err, done);
 }
+// Whether launch_gated_scan launches a kernel for n bytes (and so can report
+// a completion).
+inline bool gated_scan_launches(const DeviceMachine &dm, uint64_t n) { return dm.gate_bits ? n > 0 : n >= 6; }
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                      std::string &err);

@@ -2,12 +2,14 @@
 // the scheduler of serve_sched.h over a HIP device.
 //
 // Each slot owns one HIP stream. A request's work is queued on its slot's
-// stream alone, in order: the copy of a host text into the pool, the scan,
-// and a one-thread kernel that publishes the match total and the run's
-// sequence number to the slot's completion word in pinned host memory (and
-// clears the device count for the slot's next run). So nothing on one slot
-// ever waits on another, and the scheduler sees completions by reading host
-// memory, with no runtime call in its polling.
+// stream alone, in order: the copy of a host text into the pool, then the
+// scan, whose last workgroup publishes the match total and the run's
+// sequence number to the slot's completion word in pinned host memory and
+// clears the slot's device counters for its next run (one launch per request;
+// the DFA path and texts too short for a launch publish with a one-thread
+// kernel instead). So nothing on one slot ever waits on another, and the
+// scheduler sees completions by reading host memory, with no runtime call in
+// its polling.
 //
 // The scan: automata whose start-position gate passes few windows are
 // scanned in one gated launch (AC_ALGO_GATED); the others with the DFA, in
@@ -44,7 +46,12 @@ __global__ void publish_kernel(unsigned long long *count, uint64_t *word, uint64
     *count = 0;
 }
 
-__global__ void zero_count_kernel(unsigned long long *count) { *count = 0; }
+__global__ void zero_slot_kernel(unsigned long long *count, unsigned int *finished) {
+    *count = 0;
+    *finished = 0;
+}
+
+constexpr size_t kSlotWordBytes = 32;
 
 class HipDevice final : public Device {
 public:
@@ -52,13 +59,14 @@ public:
         hipStream_t stream = nullptr;
         unsigned long long *d_count = nullptr;  // device: the run's match count
         uint32_t *d_state = nullptr;            // device: two carried-state words, used in turn
+        unsigned int *d_finished = nullptr;     // device: workgroups of the run's scan done
     };
 
     int device = -1;
     uint64_t piece = 0;
     uint8_t *pool_base = nullptr;
     std::vector<Slot> slots;
-    void *words = nullptr;      // device words of every slot (count, two state words)
+    void *words = nullptr;      // device words of every slot (count, two state words, finish counter)
     uint64_t *h_words = nullptr;  // pinned host: two completion words per slot (total, sequence)
     const ac_automaton *autos[acm::serve::kMaxAutos] = {};
     std::atomic<uint32_t> n_autos{0};
@@ -80,9 +88,9 @@ public:
             pool_base = nullptr;
             return e;
         }
-        // per slot: count (8 bytes) and two state words, 16 bytes in all
-        e = hipMalloc(&words, size_t(n_slots) * 16);
-        if (e == hipSuccess) e = hipMemset(words, 0, size_t(n_slots) * 16);
+        // per slot: count (8 bytes), two state words, the finish counter
+        e = hipMalloc(&words, size_t(n_slots) * kSlotWordBytes);
+        if (e == hipSuccess) e = hipMemset(words, 0, size_t(n_slots) * kSlotWordBytes);
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void **>(&h_words), size_t(n_slots) * 16, hipHostMallocCoherent);
         if (e != hipSuccess) return e;
@@ -90,8 +98,10 @@ public:
         slots.resize(n_slots);
         for (uint32_t i = 0; i < n_slots && e == hipSuccess; ++i) {
             Slot &sl = slots[i];
-            sl.d_count = reinterpret_cast<unsigned long long *>(static_cast<uint8_t *>(words) + 16 * i);
-            sl.d_state = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(words) + 16 * i + 8);
+            uint8_t *base = static_cast<uint8_t *>(words) + kSlotWordBytes * i;
+            sl.d_count = reinterpret_cast<unsigned long long *>(base);
+            sl.d_state = reinterpret_cast<uint32_t *>(base + 8);
+            sl.d_finished = reinterpret_cast<unsigned int *>(base + 16);
             e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         }
         return e;
@@ -129,9 +139,16 @@ public:
         }
         uint64_t *count = reinterpret_cast<uint64_t *>(sl.d_count);
         int rc = AC_OK;
+        bool published = false;
         if (acm::auto_algo(a) == AC_ALGO_GATED) {
             *pieces = 1;
-            rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err);
+            if (acm::gated_scan_launches(a->dm, w.n)) {
+                const acm::Completion c{sl.d_finished, h_words + 2 * slot, w.seq};
+                rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err, &c);
+                published = true;
+            } else {
+                rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err);
+            }
         } else {
             acm::ScanConfig cfg;
             cfg.algo = AC_ALGO_DFA;
@@ -148,6 +165,7 @@ public:
             }
         }
         if (rc != AC_OK) return rc;
+        if (published) return AC_OK;
         hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(1), 0, sl.stream, sl.d_count, h_words + 2 * slot, w.seq);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
@@ -167,7 +185,7 @@ public:
         bind_thread();
         Slot &sl = slots[slot];
         (void)hipStreamSynchronize(sl.stream);
-        hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, sl.stream, sl.d_count);
+        hipLaunchKernelGGL(zero_slot_kernel, dim3(1), dim3(1), 0, sl.stream, sl.d_count, sl.d_finished);
         (void)hipStreamSynchronize(sl.stream);
     }
 
