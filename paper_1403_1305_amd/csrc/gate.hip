@@ -15,8 +15,10 @@
 // and owns the last 1008 of them: lane 0 holds the 16 bytes before, so that
 // every lane finds the 9 bytes before its own in the lane below it and tests
 // the 16 windows that end in its bytes. Steps are handed to the waves of the
-// grid in turn. Starts that pass both levels go to a per-wave queue in LDS;
-// whenever 63 or more wait, the wave walks up to 64 of them, one per lane.
+// grid in turn. Starts that pass the first level go to a per-wave queue in
+// LDS; there they are tested against the second level 64 at a time, and
+// whenever 63 or more have passed both, the wave walks 64 of them, one per
+// lane.
 // Every start position belongs to the one window that begins at it, so each
 // occurrence is found once.
 #include <algorithm>
@@ -153,30 +155,59 @@ __device__ __forceinline__ void walk_starts(const GateArgs &a, bool has, uint32_
     walk_on(a, has && d == kGateQ && run == kGateQ, x, p + kGateQ, em);
 }
 
-// Walk up to 64 of the qn starts queued at q (entries {start, window code}),
-// one per lane; returns how many wait afterwards.
+// Queue entries are {start, classes of the 12 bytes from the start (first
+// byte in the lowest bits) | kNoSecond when the second level does not apply}.
+constexpr uint32_t kNoSecond = 0x80000000u;
+
+// Walk up to 64 of the qn starts queued at q, one per lane; returns how many
+// wait afterwards.
 __device__ __forceinline__ uint32_t drain_starts(const GateArgs &a, const uint2 *q, uint32_t qn, Emitter &em) {
     const uint32_t lane = __lane_id();
     const uint32_t took = min(qn, 64u);
     __builtin_amdgcn_wave_barrier();
     const uint2 e = lane < took ? q[qn - took + lane] : make_uint2(0u, 0u);
     __builtin_amdgcn_wave_barrier();
-    walk_starts(a, lane < took, e.x, e.y, em);
+    walk_starts(a, lane < took, e.x, e.y & (kGateCodes - 1u), em);
     return qn - took;
+}
+
+// Test the queued starts [qf, qn) against the second level, 64 at a time (one
+// LDS read for all of them), and keep those that pass, in order, from qf on;
+// returns the queue's new length. A round reads all its entries before it
+// writes any, and writes only at or below the lowest index it read.
+__device__ __forceinline__ uint32_t filter_starts(const uint32_t *s_bits2, uint2 *q, uint32_t qf, uint32_t qn) {
+    const uint32_t lane = __lane_id();
+    uint32_t wr = qf;
+    for (uint32_t rd = qf; rd < qn; rd += 64u) {
+        const uint32_t t = min(qn - rd, 64u);
+        __builtin_amdgcn_wave_barrier();
+        const uint2 e = lane < t ? q[rd + lane] : make_uint2(0u, 0u);
+        bool keep = false;
+        if (lane < t) {
+            const uint32_t h = gate2_hash(e.y & 0xffffffu);
+            keep = (e.y & kNoSecond) != 0u || __builtin_amdgcn_ubfe(s_bits2[h >> 5], h, 1u) != 0u;
+        }
+        const uint64_t ks = __ballot(keep);
+        __builtin_amdgcn_wave_barrier();
+        if (keep) q[wr + lane_rank(ks)] = e;
+        wr += uint32_t(__popcll(ks));
+    }
+    return wr;
 }
 
 // The windows of one wave step. Lane l (l >= 1) owns the 16 bytes at pos and
 // holds their classes in W; P holds the lane below's (the 16 bytes before),
 // Wn the lane above's. `valid` masks the windows (by their last byte) that
-// lie inside the text. With SECOND, a window that passes the first level is
-// kept only if its 12-byte class string passes the second (where the lane
-// holds those bytes). Kept starts are queued at q (qn of them waiting, the
-// same in every lane); whenever 63 or more wait (a queue below 63 takes a
-// round's at most 63 new ones) up to 64 are walked.
+// lie inside the text. Starts that pass the first level are queued at q with
+// their 12-byte class string (qn queued, the first qf of them already through
+// the second level; the same in every lane). With SECOND the second level
+// applies where the lane holds those 12 bytes. Whenever 63 or more wait (a
+// queue below 63 takes a round's at most 63 new ones) the new ones are
+// filtered, and if 63 or more remain, 64 are walked.
 template <bool SECOND>
 __device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *s_bits, const uint32_t *s_bits2,
                                              uint32_t W, uint32_t P, uint32_t Wn, uint32_t pos, uint32_t valid,
-                                             uint2 *q, uint32_t &qn, Emitter &em) {
+                                             uint2 *q, uint32_t &qn, uint32_t &qf, Emitter &em) {
     const uint32_t lane = __lane_id();
     // window ending at byte j of the lane: classes of bytes j-9 .. j, bits
     // 14 + 2j on in the 64-bit word P:W
@@ -189,29 +220,26 @@ __device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *
         m |= __builtin_amdgcn_ubfe(word, r, 1u) << j;
     }
     m &= valid;
+    // no LDS read here: the queue takes every start that passed, and the
+    // second level is tested on 64 queued starts at once (filter_starts)
     while (true) {
         const uint64_t has = __ballot(m != 0);
         if (has == 0) break;
-        bool keep = false;
-        uint32_t p = 0, code = 0;
         if (m) {
             const uint32_t j = uint32_t(__builtin_ctz(m));
             m &= m - 1u;
             // classes of bytes j-9 .. j+6 of the lane (the window and what follows)
             const uint32_t r = j <= 8 ? __builtin_amdgcn_alignbit(W, P, 14u + 2u * j)
                                       : __builtin_amdgcn_alignbit(Wn, W, 2u * j - 18u);
-            code = r & (kGateCodes - 1u);
-            p = pos + j - (kGateQ - 1);
-            keep = true;
-            if (SECOND && (lane < 63 || j < 14)) {
-                const uint32_t h = gate2_hash(r & 0xffffffu);
-                keep = __builtin_amdgcn_ubfe(s_bits2[h >> 5], h, 1u) != 0u;
-            }
+            const bool second = SECOND && (lane < 63 || j < 14);
+            q[qn + lane_rank(has)] = make_uint2(pos + j - (kGateQ - 1), (r & 0xffffffu) | (second ? 0u : kNoSecond));
         }
-        const uint64_t ks = __ballot(keep);
-        if (keep) q[qn + lane_rank(ks)] = make_uint2(p, code);
-        qn += uint32_t(__popcll(ks));
-        if (qn >= 63) qn = drain_starts(a, q, qn, em);
+        qn += uint32_t(__popcll(has));
+        if (qn >= 63) {
+            qn = filter_starts(s_bits2, q, qf, qn);
+            if (qn >= 63) qn = drain_starts(a, q, qn, em);
+            qf = qn;
+        }
     }
 }
 
@@ -234,7 +262,7 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
     }
     __syncthreads();
     uint2 *q = s_queue + wave * kStartQueue;
-    uint32_t qn = 0;  // queued starts (the same in every lane)
+    uint32_t qn = 0, qf = 0;  // queued starts, and how many passed the second level (the same in every lane)
 
     const uint32_t W = gridDim.x * kGateWaves, gw = blockIdx.x * kGateWaves + wave;
     const uint32_t n_tiles = uint32_t((uint64_t(a.n) + kOwnBytes - 1) / kOwnBytes);
@@ -259,7 +287,7 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
             const uint32_t P = __shfl_up(Wd, 1);
             const uint32_t Wn = __shfl_down(Wd, 1);
             const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
-            step_windows<true>(a, s_bits, s_bits2, Wd, P, Wn, pos, lane ? 0xffffu : 0u, q, qn, em);
+            step_windows<true>(a, s_bits, s_bits2, Wd, P, Wn, pos, lane ? 0xffffu : 0u, q, qn, qf, em);
         }
     }
     // the first tile and a last, partial one: loads and windows checked
@@ -279,9 +307,10 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
             for (uint32_t j = 0; j < 16; ++j)
                 if (base + j >= kGateQ - 1 && base + j < int64_t(a.n)) valid |= 1u << j;
         }
-        step_windows<false>(a, s_bits, s_bits2, Wd, P, Wn, uint32_t(base), valid, q, qn, em);
+        step_windows<false>(a, s_bits, s_bits2, Wd, P, Wn, uint32_t(base), valid, q, qn, qf, em);
     }
-    if (qn) drain_starts(a, q, qn, em);
+    qn = filter_starts(s_bits2, q, qf, qn);
+    while (qn) qn = drain_starts(a, q, qn, em);
     // starts too close to the end for a whole window: walked from the root
     if (gw == 0) {
         const uint32_t from = a.n > kGateQ - 1 ? a.n - (kGateQ - 1) : 0u;
