@@ -228,7 +228,7 @@ def bench_batched(args, torch, ac, stream):
     slot = np.concatenate([[0], np.cumsum(per_text)]).astype(np.int64)
     counts = torch.zeros(len(offs), dtype=torch.int64, device="cuda")
     out2 = torch.empty(max(1, matches), dtype=torch.int64, device="cuda")
-    popts = ac._scan_opts(ac.AC_ALGO_DFA, 0, 0, 0)
+    popts = ac._scan_opts(ac.AC_ALGO_AUTO, 0, 0, 0)  # each text with the matcher AUTO picks for it
 
     def plain(i):
         for t in range(len(offs)):
@@ -254,7 +254,7 @@ def bench_batched(args, torch, ac, stream):
         "n_texts": len(offs), "text_bytes": total, "automata": len(autos),
         "states_min_max": [min(states), max(states)], "matches": matches,
         "graph_ms": round(kernel_ms, 4), "eager_ms": round(float(np.mean(ms_eager)), 4),
-        "plan": {k: info[k] for k in ("placement", "walkers", "chunk", "threads", "grid", "n_tasks")},
+        "plan": {k: info[k] for k in ("algo", "placement", "walkers", "chunk", "threads", "grid", "n_tasks")},
         "autotune": {"choice": report["choice"], "tune_s": round(report["tune_s"], 2),
                      "candidates": len(report.get("candidates", []))},
         "plain_per_text": {"value": round(total * len(pms) / pwall / 1e9, 3), "unit": "GB/s",

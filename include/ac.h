@@ -324,20 +324,29 @@ int ac_sort_matches(uint64_t *d_keys, uint64_t count, void *d_tmp, uint64_t tmp_
 typedef struct ac_batch ac_batch;
 
 typedef struct {
-    uint32_t placement; /* AC_PLACE_AUTO (LDS_HOT when every automaton has an LDS
-                           image, else GLOBAL), AC_PLACE_LDS_HOT or AC_PLACE_GLOBAL */
-    uint32_t walkers;   /* chunks walked per lane (1 to 4); 0 = by placement */
-    uint32_t chunk;     /* end positions per work item; 0 = from the batch size */
-    uint32_t reserved;
+    uint32_t placement; /* DFA: AC_PLACE_AUTO (LDS_HOT when every automaton has an
+                           LDS image, else GLOBAL), AC_PLACE_LDS_HOT or AC_PLACE_GLOBAL */
+    uint32_t walkers;   /* DFA: chunks walked per lane (1 to 4); 0 = by placement */
+    uint32_t chunk;     /* DFA: end positions per work item; gated: start positions
+                           per task (rounded to whole 1,008-byte tiles); 0 = from
+                           the batch size */
+    uint32_t algo;      /* ac_batch_create: AC_ALGO_AUTO (GATED when every automaton
+                           has the class gate and AC_ALGO_AUTO would pick GATED for
+                           it, else DFA), AC_ALGO_DFA or AC_ALGO_GATED (the gated
+                           failure-less scan, tasks of whole tiles of one text taken
+                           from a device counter, LDS bitmaps loaded per automaton).
+                           ac_scan_batch: AUTO or DFA */
 } ac_batch_tune;
 
 typedef struct {
-    uint32_t placement, walkers, block_bytes, chunk;
+    uint32_t placement, walkers, block_bytes, chunk;  /* DFA plans; gated: 0, 0, 0, task bytes */
     uint32_t threads;  /* per workgroup */
     uint32_t grid;     /* workgroups of the persistent launch */
-    uint32_t n_items;  /* work items (chunks of texts) */
+    uint32_t n_items;  /* work items (chunks of texts; gated: tasks) */
     uint32_t n_tasks;  /* runs of items of one automaton, split over the grid */
     uint64_t text_bytes;
+    uint32_t algo;     /* AC_ALGO_DFA or AC_ALGO_GATED */
+    uint32_t pad;
 } ac_batch_info_t;
 
 /*

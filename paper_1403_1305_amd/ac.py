@@ -81,7 +81,7 @@ class ac_scan_opts(ctypes.Structure):
 
 class ac_batch_tune(ctypes.Structure):
     _fields_ = [("placement", ctypes.c_uint32), ("walkers", ctypes.c_uint32),
-                ("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("chunk", ctypes.c_uint32), ("algo", ctypes.c_uint32)]
 
 
 class ac_batch_info_t(ctypes.Structure):
@@ -89,7 +89,7 @@ class ac_batch_info_t(ctypes.Structure):
                 ("block_bytes", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
                 ("threads", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("n_items", ctypes.c_uint32), ("n_tasks", ctypes.c_uint32),
-                ("text_bytes", ctypes.c_uint64)]
+                ("text_bytes", ctypes.c_uint64), ("algo", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class ac_serve_opts(ctypes.Structure):

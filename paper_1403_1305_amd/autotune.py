@@ -1,11 +1,13 @@
 """Autotuner for the batched scan.
 
-Picks the table placement (LDS image + global cold rows, or global table),
-the number of chunks each lane walks (1 to 4) and the chunk length for a
-batch by timing candidate plans on the device with HIP events, then caches
-the winner under a key of (GPU architecture, byte-class scheme, largest
-automaton's state count, total text bytes, number of texts), each size
-rounded to a power of two.
+Picks the matcher (the gated failure-less scan when every automaton has the
+class gate, or the chunked DFA), and for the DFA the table placement (LDS
+image + global cold rows, or global table), the number of chunks each lane
+walks (1 to 4) and the chunk length, for the gated scan the task length, by
+timing candidate plans on the device with HIP events. The winner is cached
+under a key of (GPU architecture, byte-class scheme, largest automaton's
+state count, total text bytes, number of texts), each size rounded to a
+power of two.
 
 The input split follows the paper's data-parallel reading (§III: the input
 is divided among workers, and several machines may serve the same input,
@@ -28,6 +30,7 @@ CACHE_ENV = "AC_TUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1403_1305_amd", "batch_tune.json")
 CHUNKS = (0, 128, 256, 512, 1024, 2048, 4096)  # 0 = the plan's own choice
 WALKERS = (1, 2, 3, 4)
+GATED_TASKS = (0, 256 * 1008, 4096 * 1008)  # gated plans: start positions per task, 0 = the plan's choice
 
 
 def _log2_bucket(x: int) -> int:
@@ -41,19 +44,23 @@ def tune_key(autos, text_len, arch: str | None = None) -> str:
     states = max(i["n_states"] for i in infos)
     total = int(np.sum(np.asarray(text_len, dtype=np.uint64)))
     return (f"{arch}|{scheme}|S{_log2_bucket(states)}|T{_log2_bucket(total)}"
-            f"|n{_log2_bucket(len(text_len))}")
+            f"|n{_log2_bucket(len(text_len))}|v2")
 
 
 def candidates(autos):
-    """(placement, walkers, chunk) triples valid for these automata."""
-    images = all(ac.ac_info(a)["hot_states"] > 0 for a in autos)
+    """(algo, placement, walkers, chunk) tuples valid for these automata."""
+    infos = [ac.ac_info(a) for a in autos]
+    images = all(i["hot_states"] > 0 for i in infos)
     places = [ac.AC_PLACE_LDS_HOT, ac.AC_PLACE_GLOBAL] if images else [ac.AC_PLACE_GLOBAL]
-    return [(p, w, c) for p in places for w in WALKERS for c in CHUNKS]
+    cands = [(ac.AC_ALGO_DFA, p, w, c) for p in places for w in WALKERS for c in CHUNKS]
+    if all(i["has_gate"] == 1 for i in infos):
+        cands += [(ac.AC_ALGO_GATED, 0, 0, c) for c in GATED_TASKS]
+    return cands
 
 
-def make_tune(placement: int, walkers: int, chunk: int) -> ac.ac_batch_tune:
+def make_tune(algo: int, placement: int, walkers: int, chunk: int) -> ac.ac_batch_tune:
     t = ac.ac_batch_tune()
-    t.placement, t.walkers, t.chunk = placement, walkers, chunk
+    t.algo, t.placement, t.walkers, t.chunk = algo, placement, walkers, chunk
     return t
 
 
@@ -99,28 +106,28 @@ def tune_batch(autos, d_text, text_off, text_len, text_auto, out, cap, count, re
     cache = _load_cache(path) if use_cache else {}
     t0 = time.perf_counter()
     if key in cache:
-        p, w, c = cache[key]["choice"]
-        tune = make_tune(p, w, c)
+        g, p, w, c = cache[key]["choice"]
+        tune = make_tune(g, p, w, c)
         batch = ac.ac_batch_create(autos, text_off, text_len, text_auto, tune=tune, stream=stream)
         return batch, tune, {"key": key, "cached": True, "tune_s": time.perf_counter() - t0,
-                             "choice": [p, w, c]}
+                             "choice": [g, p, w, c]}
     timings = []
     best = None
-    for p, w, c in candidates(autos):
-        tune = make_tune(p, w, c)
+    for g, p, w, c in candidates(autos):
+        tune = make_tune(g, p, w, c)
         batch = ac.ac_batch_create(autos, text_off, text_len, text_auto, tune=tune, stream=stream)
         ms = time_plan(batch, d_text, out, cap, count, reps, stream)
         info = ac.ac_batch_info(batch)
-        timings.append({"placement": p, "walkers": w, "chunk": info["chunk"], "ms": round(ms, 4)})
+        timings.append({"algo": g, "placement": p, "walkers": w, "chunk": info["chunk"], "ms": round(ms, 4)})
         if best is None or ms < best[0]:
-            best = (ms, (p, w, c))
+            best = (ms, (g, p, w, c))
         ac.ac_batch_free(batch)
-    p, w, c = best[1]
-    tune = make_tune(p, w, c)
+    g, p, w, c = best[1]
+    tune = make_tune(g, p, w, c)
     batch = ac.ac_batch_create(autos, text_off, text_len, text_auto, tune=tune, stream=stream)
     if use_cache:
         cache = _load_cache(path)
-        cache[key] = {"choice": [p, w, c], "ms": round(best[0], 4)}
+        cache[key] = {"choice": [g, p, w, c], "ms": round(best[0], 4)}
         _store_cache(path, cache)
     return batch, tune, {"key": key, "cached": False, "tune_s": time.perf_counter() - t0,
-                         "choice": [p, w, c], "candidates": timings}
+                         "choice": [g, p, w, c], "candidates": timings}

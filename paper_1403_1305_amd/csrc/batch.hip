@@ -25,6 +25,9 @@
 
 struct ac_batch {
     int device = -1;
+    bool gated = false;  // the gated plan (tasks of tiles) rather than the DFA's items
+    acm::GateTask *d_gtasks = nullptr;
+    void *d_gautos = nullptr;  // per automaton: the gated scan's argument block
     uint32_t placement = AC_PLACE_GLOBAL, walkers = 1, block_bytes = 128, chunk = 0;
     uint32_t block = 256, lds = 0, grid = 1;
     uint32_t n_items = 0, n_tasks = 0, n_texts = 0, n_autos = 0;
@@ -56,6 +59,10 @@ void release(ac_batch *b) {
     if (b->d_tasks) (void)hipFree(b->d_tasks);
     if (b->d_autos) (void)hipFree(b->d_autos);
     if (b->d_next) (void)hipFree(b->d_next);
+    if (b->d_gtasks) (void)hipFree(b->d_gtasks);
+    if (b->d_gautos) (void)hipFree(b->d_gautos);
+    b->d_gtasks = nullptr;
+    b->d_gautos = nullptr;
     b->exec = nullptr;
     b->graph = nullptr;
     b->capture = nullptr;
@@ -94,6 +101,11 @@ int launch(ac_batch *b, const uint8_t *text, uint64_t *out, uint64_t cap, uint64
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(AC_ERR_HIP, std::string("batch reset launch: ") + hipGetErrorString(e));
     if (b->n_tasks == 0) return AC_OK;
+    if (b->gated) {
+        const int rc = acm::launch_gate_batch(text, b->d_gtasks, b->n_tasks, b->d_gautos, out, cap, count,
+                                              b->d_next, b->grid, s, err);
+        return rc == AC_OK ? AC_OK : set_error(rc, err);
+    }
     acm::dfa::BatchArgs args{};
     args.text = text;
     args.items = b->d_items;
@@ -318,6 +330,8 @@ int prepare_one_shot(const char *fn, const ac_automaton *const *autos, uint32_t 
     const uint32_t K = tune && tune->walkers ? tune->walkers : (place == AC_PLACE_LDS_HOT ? 2u : 1u);
     if (K < 1 || K > 4) return set_error(AC_ERR_INVALID, f() + ": walkers must be 1, 2, 3 or 4");
     if (tune && tune->chunk % 16) return set_error(AC_ERR_INVALID, f() + ": chunk must be a multiple of 16");
+    if (tune && tune->algo != AC_ALGO_AUTO && tune->algo != AC_ALGO_DFA)
+        return set_error(AC_ERR_INVALID, f() + ": the one-shot batch scans with the DFA (algo AUTO or DFA)");
     o.walkers_per_lane = K;
     o.bb = K >= 3 ? 64u : 128u;
     const bool hashed = autos[0]->m.hashed;
@@ -442,6 +456,92 @@ int scratch_address(int dev, uint8_t **out) {
     return AC_OK;
 }
 
+// The gated plan: every text cut into tasks of whole tiles (at most `per`
+// tiles each), ordered by automaton; one per-automaton argument block.
+int create_gated(const ac_automaton *const *autos, uint32_t n_autos, const uint64_t *text_off,
+                 const uint64_t *text_len, const uint32_t *text_auto, uint32_t n_texts, const ac_batch_tune *tune,
+                 void *stream, int dev, ac_batch **out) {
+    const uint64_t tile = acm::gate_batch_tile_bytes();
+    uint64_t total = 0, tiles = 0;
+    for (uint32_t t = 0; t < n_texts; ++t) {
+        if (text_auto[t] >= n_autos)
+            return set_error(AC_ERR_INVALID, "ac_batch_create: text " + std::to_string(t) + " names automaton " +
+                                                 std::to_string(text_auto[t]) + " of " + std::to_string(n_autos));
+        if (text_len[t] && (text_off[t] & 15u))
+            return set_error(AC_ERR_INVALID, "ac_batch_create: text offsets must be multiples of 16");
+        if (text_off[t] + text_len[t] >= (1ull << 32) || text_len[t] >= (1ull << 32))
+            return set_error(AC_ERR_TOO_LARGE, "ac_batch_create: the batch buffer must stay below 2^32 bytes");
+        total += text_len[t];
+        tiles += (text_len[t] + tile - 1) / tile;
+    }
+    const uint32_t grid_max = uint32_t(acm::compute_units(dev));  // one workgroup per CU (the bitmaps fill the LDS)
+    uint64_t per = tune && tune->chunk ? (tune->chunk + tile - 1) / tile : 0;
+    if (per == 0) {
+        // about kRounds tasks per workgroup, so that the hand-out evens out
+        // texts and automata of different cost
+        constexpr uint64_t kRounds = 8;
+        per = std::max<uint64_t>(16, (tiles + grid_max * kRounds - 1) / (grid_max * kRounds));
+    }
+    std::unique_ptr<ac_batch> b(new (std::nothrow) ac_batch());
+    if (!b) return set_error(AC_ERR_NOMEM, "ac_batch_create: out of host memory");
+    b->device = dev;
+    b->gated = true;
+    b->placement = 0;
+    b->walkers = 0;
+    b->block_bytes = 0;
+    b->chunk = uint32_t(std::min<uint64_t>(per * tile, 1u << 30));
+    b->block = 1024;
+    b->n_texts = n_texts;
+    b->n_autos = n_autos;
+    b->text_bytes = total;
+    std::vector<uint32_t> order(n_texts);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return text_auto[x] < text_auto[y]; });
+    std::vector<acm::GateTask> tasks;
+    std::vector<uint8_t> blob;
+    try {
+        for (uint32_t t : order) {
+            const uint64_t nt = (text_len[t] + tile - 1) / tile;
+            for (uint64_t t0 = 0; t0 < nt; t0 += per) {
+                acm::GateTask g{};
+                g.off = uint32_t(text_off[t]);
+                g.len = uint32_t(text_len[t]);
+                g.t0 = uint32_t(t0);
+                g.t1 = uint32_t(std::min(nt, t0 + per));
+                g.automaton = text_auto[t];
+                tasks.push_back(g);
+            }
+        }
+        blob.resize(size_t(n_autos) * acm::gate_batch_auto_bytes());
+    } catch (const std::bad_alloc &) {
+        return set_error(AC_ERR_NOMEM, "ac_batch_create: out of host memory");
+    }
+    for (uint32_t i = 0; i < n_autos; ++i)
+        acm::fill_gate_batch_auto(autos[i]->dm, blob.data() + size_t(i) * acm::gate_batch_auto_bytes());
+    b->n_items = b->n_tasks = uint32_t(tasks.size());
+    b->grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(grid_max, tasks.size())));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc;
+    const std::vector<uint32_t> next(1, 0u);
+    uint8_t *d_blob = nullptr;
+    if ((rc = upload(tasks, &b->d_gtasks, s)) || (rc = upload(blob, &d_blob, s)) || (rc = upload(next, &b->d_next, s))) {
+        b->d_gautos = d_blob;
+        (void)hipStreamSynchronize(s);
+        release(b.get());
+        return rc;
+    }
+    b->d_gautos = d_blob;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        release(b.get());
+        return set_error(AC_ERR_HIP, std::string("ac_batch_create: ") + hipGetErrorString(e));
+    }
+    *out = b.release();
+    return AC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -469,6 +569,18 @@ int ac_batch_create(const ac_automaton *const *autos, uint32_t n_autos, const ui
                              "alphabet layout); split the batch by alphabet");
         all_images &= a->m.hot_states > 0;
     }
+    const uint32_t algo = tune ? tune->algo : AC_ALGO_AUTO;
+    if (algo != AC_ALGO_AUTO && algo != AC_ALGO_DFA && algo != AC_ALGO_GATED)
+        return set_error(AC_ERR_INVALID, "ac_batch_create: algo must be AUTO, DFA or GATED");
+    bool all_gates = true, all_auto_gated = true;
+    for (uint32_t i = 0; i < n_autos; ++i) {
+        all_gates &= autos[i]->dm.gate_bits != nullptr;
+        all_auto_gated &= autos[i]->dm.gate_bits != nullptr && acm::auto_algo(autos[i]) == AC_ALGO_GATED;
+    }
+    if (algo == AC_ALGO_GATED && !all_gates)
+        return set_error(AC_ERR_INVALID, "ac_batch_create: AC_ALGO_GATED needs the class gate in every automaton");
+    if (algo == AC_ALGO_GATED || (algo == AC_ALGO_AUTO && all_auto_gated))
+        return create_gated(autos, n_autos, text_off, text_len, text_auto, n_texts, tune, stream, dev, out);
     const uint32_t want_place = tune ? tune->placement : AC_PLACE_AUTO;
     uint32_t place = want_place == AC_PLACE_AUTO ? (all_images ? AC_PLACE_LDS_HOT : AC_PLACE_GLOBAL) : want_place;
     if (place != AC_PLACE_LDS_HOT && place != AC_PLACE_GLOBAL)
@@ -612,6 +724,8 @@ int ac_batch_info(const ac_batch *b, ac_batch_info_t *info) {
     info->n_items = b->n_items;
     info->n_tasks = b->n_tasks;
     info->text_bytes = b->text_bytes;
+    info->algo = b->gated ? AC_ALGO_GATED : AC_ALGO_DFA;
+    info->pad = 0;
     return AC_OK;
 }
 

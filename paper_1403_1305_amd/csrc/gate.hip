@@ -22,6 +22,7 @@
 // Every start position belongs to the one window that begins at it, so each
 // occurrence is found once.
 #include <algorithm>
+#include <cstring>
 
 #include "device_common.h"
 #include "machine.h"
@@ -47,6 +48,7 @@ static_assert(kGateQ == 10 && kGateQ2 == 12, "the window extraction below assume
 struct GateArgs {
     const uint8_t *text;
     uint32_t n;
+    uint32_t base;            // added to every reported end position
     uint32_t shift;           // class of byte b = (b >> shift) & 3
     uint32_t letters;         // byte c = the letter of class c
     const uint32_t *bits, *bits2, *node, *go, *own_off, *own_ids, *path_off, *path_ids, *pat_len;
@@ -122,7 +124,7 @@ __device__ __forceinline__ void walk_on(const GateArgs &a, bool active, uint32_t
                 if (active) x = g & kStateMask;
             }
         }
-        emit_set(em, active && (g & kAccept), x, i, a.own_off, a.own_ids);
+        emit_set(em, active && (g & kAccept), x, i + a.base, a.own_off, a.own_ids);
         ++i;
     }
 }
@@ -149,7 +151,7 @@ __device__ __forceinline__ void walk_starts(const GateArgs &a, bool has, uint32_
         const bool h = k < ke;
         const uint32_t id = h ? a.path_ids[k] : 0u;
         const uint32_t len = h ? a.pat_len[id] : 0u;
-        em.emit(h && len <= run, (uint64_t(p + len - 1) << 32) | id);
+        em.emit(h && len <= run, (uint64_t(p + len - 1 + a.base) << 32) | id);
         k += h ? 1u : 0u;
     }
     walk_on(a, has && d == kGateQ && run == kGateQ, x, p + kGateQ, em);
@@ -243,34 +245,34 @@ __device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *
     }
 }
 
-__global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
-    // static LDS: the bitmaps' addresses are then constants the lookups fold in
-    __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
-    __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
-    __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
-    __shared__ __align__(16) uint8_t s_emit[kGateWaves * kQueueBytesPerWave];
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x & 63u;
-    Emitter em;
-    em.init(s_emit, a.out, a.cap, a.count);
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.bits);
-        uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
-        for (uint32_t i = threadIdx.x; i < kBitmapWords / 4; i += kGateBlock) dst[i] = src[i];
-        const uint4 *src2 = reinterpret_cast<const uint4 *>(a.bits2);
-        uint4 *dst2 = reinterpret_cast<uint4 *>(s_bits2);
-        for (uint32_t i = threadIdx.x; i < kBitmap2Words / 4; i += kGateBlock) dst2[i] = src2[i];
-    }
-    __syncthreads();
-    uint2 *q = s_queue + wave * kStartQueue;
-    uint32_t qn = 0, qf = 0;  // queued starts, and how many passed the second level (the same in every lane)
+// Copy an automaton's two bitmaps into LDS (every thread of the workgroup
+// takes part; the caller synchronises).
+__device__ __forceinline__ void load_bitmaps(const GateArgs &a, uint32_t *s_bits, uint32_t *s_bits2) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.bits);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
+    for (uint32_t i = threadIdx.x; i < kBitmapWords / 4; i += kGateBlock) dst[i] = src[i];
+    const uint4 *src2 = reinterpret_cast<const uint4 *>(a.bits2);
+    uint4 *dst2 = reinterpret_cast<uint4 *>(s_bits2);
+    for (uint32_t i = threadIdx.x; i < kBitmap2Words / 4; i += kGateBlock) dst2[i] = src2[i];
+}
 
-    const uint32_t W = gridDim.x * kGateWaves, gw = blockIdx.x * kGateWaves + wave;
+// The start positions of tiles [t0, t1) of the text (tile t = the 1,008
+// starts from t * 1008), taken by this wave (gw) of W waves in turn: every
+// start of the range is tested, the passing ones walked, and with the text's
+// last tile also the starts too close to its end for a whole window. The
+// wave's queue is empty again on return.
+__device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_bits, const uint32_t *s_bits2,
+                                           uint2 *q, Emitter &em, uint32_t t0, uint32_t t1, uint32_t gw,
+                                           uint32_t W) {
+    const uint32_t lane = __lane_id();
+    uint32_t qn = 0, qf = 0;  // queued starts, and how many passed the second level (the same in every lane)
     const uint32_t n_tiles = uint32_t((uint64_t(a.n) + kOwnBytes - 1) / kOwnBytes);
     // tiles whose 1 KiB lies inside the text, the first excepted (its lane 0
-    // would read before byte 0): t = first, first + W, ... < full
+    // would read before byte 0): [lo, hi), wave gw taking lo + gw, lo + gw + W, ...
     const uint32_t full = a.n / kOwnBytes;
-    const uint32_t first = gw == 0 ? W : gw;
-    const uint32_t cnt = full > first ? (full - first + W - 1) / W : 0u;
+    const uint32_t lo = max(t0, 1u), hi = min(t1, full);
+    const uint32_t first = lo + gw;
+    const uint32_t cnt = hi > first ? (hi - first + W - 1) / W : 0u;
     const uint8_t *lane_text = a.text + lane * kLaneBytes;  // + t * kOwnBytes - 16
     uint4 buf[kPrefetch];  // the next kPrefetch tiles of this wave, in flight
 #pragma unroll
@@ -290,11 +292,11 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
             step_windows<true>(a, s_bits, s_bits2, Wd, P, Wn, pos, lane ? 0xffffu : 0u, q, qn, qf, em);
         }
     }
-    // the first tile and a last, partial one: loads and windows checked
-    // against the text's ends, second level left out
+    // the first tile and a last, partial one, where they lie in the range:
+    // loads and windows checked against the text's ends, second level left out
     for (uint32_t e = 0; e < 2; ++e) {
         const uint32_t t = e == 0 ? 0u : n_tiles - 1u;
-        if (n_tiles == 0 || (e == 1 && (t < full || t == 0)) || gw != t % W) continue;
+        if (n_tiles == 0 || t < t0 || t >= t1 || (e == 1 && (t < full || t == 0)) || gw != e % W) continue;
         const int64_t base = int64_t(t) * kOwnBytes - 16 + int64_t(lane) * kLaneBytes;
         const uint4 v = base >= 0 && base < int64_t(a.n) ? *reinterpret_cast<const uint4 *>(a.text + base)
                                                           : make_uint4(0u, 0u, 0u, 0u);
@@ -312,12 +314,102 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
     qn = filter_starts(s_bits2, q, qf, qn);
     while (qn) qn = drain_starts(a, q, qn, em);
     // starts too close to the end for a whole window: walked from the root
-    if (gw == 0) {
+    if (t1 >= n_tiles && gw == 0) {
         const uint32_t from = a.n > kGateQ - 1 ? a.n - (kGateQ - 1) : 0u;
         walk_on(a, from + lane < a.n, 0u, from + lane, em);
     }
+}
+
+__global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
+    // static LDS: the bitmaps' addresses are then constants the lookups fold in
+    __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
+    __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
+    __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
+    __shared__ __align__(16) uint8_t s_emit[kGateWaves * kQueueBytesPerWave];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    Emitter em;
+    em.init(s_emit, a.out, a.cap, a.count);
+    load_bitmaps(a, s_bits, s_bits2);
+    __syncthreads();
+    const uint32_t n_tiles = uint32_t((uint64_t(a.n) + kOwnBytes - 1) / kOwnBytes);
+    gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, 0u, n_tiles,
+               blockIdx.x * kGateWaves + wave, gridDim.x * kGateWaves);
     em.flush();
     complete_launch(a.done, a.count);
+}
+
+// Many texts against several automata in one persistent launch: workgroups
+// take tasks (a range of tiles of one text, and its automaton) in increasing
+// order from a device counter and load an automaton's bitmaps into LDS only
+// when it differs from the previous task's. Tasks are ordered by automaton.
+// Matches go to one list, their end positions in the batch buffer.
+struct BatchLaunch {
+    const uint8_t *text;            // the batch buffer
+    const GateTask *tasks;
+    uint32_t n_tasks;
+    const GateArgs *autos;          // per automaton: tables and class scheme
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+    uint32_t *next_task;            // zero at launch
+};
+
+__global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
+    __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
+    __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
+    __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
+    __shared__ __align__(16) uint8_t s_emit[kGateWaves * kQueueBytesPerWave];
+    __shared__ uint32_t s_task;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    Emitter em;
+    em.init(s_emit, b.out, b.cap, b.count);
+    uint32_t cur = ~0u;  // automaton whose bitmaps are in LDS
+    while (true) {
+        __syncthreads();  // every wave done with the previous task (and its bitmaps)
+        if (threadIdx.x == 0) s_task = atomicAdd(b.next_task, 1u);
+        __syncthreads();
+        const uint32_t k = __builtin_amdgcn_readfirstlane(s_task);
+        if (k >= b.n_tasks) break;
+        const GateTask task = b.tasks[k];
+        GateArgs a = b.autos[task.automaton];
+        if (task.automaton != cur) {
+            load_bitmaps(a, s_bits, s_bits2);
+            __syncthreads();
+            cur = task.automaton;
+        }
+        a.text = b.text + task.off;
+        a.n = task.len;
+        a.base = task.off;
+        a.out = b.out;
+        a.cap = b.cap;
+        a.count = b.count;
+        a.done = Completion{nullptr, nullptr, 0};
+        gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, task.t0, task.t1, wave, kGateWaves);
+    }
+    em.flush();
+}
+
+}  // namespace
+
+namespace {
+
+// The machine's tables and class scheme (text, output and completion fields
+// left empty).
+GateArgs machine_args(const DeviceMachine &dm) {
+    GateArgs a{};
+    a.shift = dm.hash_shift;
+    a.letters = uint32_t(dm.hash_letter[0]) | uint32_t(dm.hash_letter[1]) << 8 |
+                uint32_t(dm.hash_letter[2]) << 16 | uint32_t(dm.hash_letter[3]) << 24;
+    a.bits = dm.gate_bits;
+    a.bits2 = dm.gate2_bits;
+    a.node = dm.gate_node;
+    a.go = dm.go;
+    a.own_off = dm.own_off;
+    a.own_ids = dm.own_ids;
+    a.path_off = dm.path_off;
+    a.path_ids = dm.path_ids;
+    a.pat_len = dm.pat_len;
+    return a;
 }
 
 }  // namespace
@@ -332,29 +424,42 @@ int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     const uint32_t cus = uint32_t(compute_units(dev));
-    GateArgs a{};
+    GateArgs a = machine_args(dm);
     a.text = text;
     a.n = uint32_t(n);
-    // one workgroup per CU (the bitmaps fill the LDS), fewer for short texts
-    const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
-    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kGateWaves - 1) / kGateWaves, cus)));
-    a.shift = dm.hash_shift;
-    a.letters = uint32_t(dm.hash_letter[0]) | uint32_t(dm.hash_letter[1]) << 8 |
-                uint32_t(dm.hash_letter[2]) << 16 | uint32_t(dm.hash_letter[3]) << 24;
-    a.bits = dm.gate_bits;
-    a.bits2 = dm.gate2_bits;
-    a.node = dm.gate_node;
-    a.go = dm.go;
-    a.own_off = dm.own_off;
-    a.own_ids = dm.own_ids;
-    a.path_off = dm.path_off;
-    a.path_ids = dm.path_ids;
-    a.pat_len = dm.pat_len;
+    a.base = 0;
     a.out = out;
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long *>(count);
     a.done = done ? *done : Completion{nullptr, nullptr, 0};
+    // one workgroup per CU (the bitmaps fill the LDS), fewer for short texts
+    const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
+    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kGateWaves - 1) / kGateWaves, cus)));
     return launch_kernel(gate_kernel, grid, kGateBlock, 0u, stream, a, err);
+}
+
+size_t gate_batch_auto_bytes() { return sizeof(GateArgs); }
+
+void fill_gate_batch_auto(const DeviceMachine &dm, void *dst) {
+    const GateArgs a = machine_args(dm);
+    std::memcpy(dst, &a, sizeof(a));
+}
+
+uint32_t gate_batch_tile_bytes() { return kOwnBytes; }
+
+int launch_gate_batch(const uint8_t *text, const GateTask *tasks, uint32_t n_tasks, const void *autos,
+                      uint64_t *out, uint64_t cap, uint64_t *count, uint32_t *next_task, uint32_t grid,
+                      hipStream_t stream, std::string &err) {
+    BatchLaunch b{};
+    b.text = text;
+    b.tasks = tasks;
+    b.n_tasks = n_tasks;
+    b.autos = static_cast<const GateArgs *>(autos);
+    b.out = out;
+    b.cap = cap;
+    b.count = reinterpret_cast<unsigned long long *>(count);
+    b.next_task = next_task;
+    return launch_kernel(gate_batch_kernel, grid, kGateBlock, 0u, stream, b, err);
 }
 
 }  // namespace acm

@@ -94,6 +94,21 @@ inline int launch_gated_scan(const DeviceMachine &dm, const uint8_t *text, uint6
 // Whether launch_gated_scan launches a kernel for n bytes (and so can report
 // a completion).
 inline bool gated_scan_launches(const DeviceMachine &dm, uint64_t n) { return dm.gate_bits ? n > 0 : n >= 6; }
+// The batched gated scan (class gate): a task is tiles [t0, t1) of the text of
+// `len` bytes at byte `off` of the batch buffer (tile t = the start positions
+// [1008 t, 1008 t + 1008) of the text), matched against automaton
+// `automaton`; tasks are ordered by automaton. The per-automaton argument
+// blocks (gate_batch_auto_bytes() each, filled by fill_gate_batch_auto) sit
+// in one device array. next_task must be zero at launch.
+struct GateTask {
+    uint32_t off, len, t0, t1, automaton, pad[3];
+};
+size_t gate_batch_auto_bytes();
+void fill_gate_batch_auto(const DeviceMachine &dm, void *dst);
+uint32_t gate_batch_tile_bytes();
+int launch_gate_batch(const uint8_t *text, const GateTask *tasks, uint32_t n_tasks, const void *autos,
+                      uint64_t *out, uint64_t cap, uint64_t *count, uint32_t *next_task, uint32_t grid,
+                      hipStream_t stream, std::string &err);
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                      std::string &err);

@@ -81,9 +81,9 @@ class BatchRun:
         return np.sort(ac.keys_to_numpy(self.out[:n]))
 
 
-def tune(placement=0, walkers=0, chunk=0):
+def tune(placement=0, walkers=0, chunk=0, algo=ac.AC_ALGO_AUTO):
     t = ac.ac_batch_tune()
-    t.placement, t.walkers, t.chunk = placement, walkers, chunk
+    t.placement, t.walkers, t.chunk, t.algo = placement, walkers, chunk, algo
     return t
 
 
@@ -101,11 +101,39 @@ def dna_batch():
 def test_batch_matches_oracle(dna_batch, placement, walkers, chunk):
     texts, sets, text_set, autos, expect = dna_batch
     note("batch", placement, walkers, chunk, "texts", len(texts))
-    r = BatchRun(autos, texts, text_set, tune=tune(placement, walkers, chunk))
+    r = BatchRun(autos, texts, text_set, tune=tune(placement, walkers, chunk, ac.AC_ALGO_DFA))
+    assert r.info["algo"] == ac.AC_ALGO_DFA
     if placement != ac.AC_PLACE_AUTO:
         assert r.info["placement"] == placement
     got = r.scan()
     assert got.size == expect.size and np.array_equal(got, expect)
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 1008, 3 * 1008, 50 * 1008])
+def test_gated_batch_matches_oracle(dna_batch, chunk):
+    """The gated plan: tasks of whole 1,008-byte tiles (one tile, three,
+    fifty, or the plan's own size), texts of every length class (empty,
+    shorter than a window, ragged, a repeated pattern), short patterns."""
+    texts, sets, text_set, autos, expect = dna_batch
+    note("gated batch", chunk)
+    r = BatchRun(autos, texts, text_set, tune=tune(chunk=chunk, algo=ac.AC_ALGO_GATED))
+    assert r.info["algo"] == ac.AC_ALGO_GATED and r.info["threads"] == 1024
+    assert np.array_equal(r.scan(), expect)
+    assert np.array_equal(r.scan(use_graph=True), expect)
+
+
+def test_gated_batch_reloads_and_long_texts():
+    """Nine automata interleaved, texts up to 1 MiB cut into many tasks:
+    workgroups cross automaton boundaries and reload their bitmaps."""
+    texts, sets, text_set = small_batch(seed=21, n_texts=120, len_hi_log2=20, n_sets=9,
+                                        set_lo=5, set_hi=3000)
+    autos = [build(s) for s in sets]
+    buf, offs, _ = ac.pack_texts(texts)
+    expect = expected(texts, sets, text_set, offs)
+    for chunk in (0, 4 * 1008):
+        r = BatchRun(autos, texts, text_set, tune=tune(chunk=chunk, algo=ac.AC_ALGO_GATED))
+        assert r.info["n_tasks"] >= len(sets)
+        assert np.array_equal(r.scan(), expect), chunk
 
 
 def test_batch_equals_plain_scans(dna_batch):
@@ -151,7 +179,7 @@ def test_batch_mixed_sizes_and_reloads():
     buf, offs, _ = ac.pack_texts(texts)
     expect = expected(texts, sets, text_set, offs)
     for w in (1, 2, 3, 4):
-        r = BatchRun(autos, texts, text_set, tune=tune(ac.AC_PLACE_LDS_HOT, w, 16))
+        r = BatchRun(autos, texts, text_set, tune=tune(ac.AC_PLACE_LDS_HOT, w, 16, ac.AC_ALGO_DFA))
         assert r.info["n_tasks"] >= len(sets)
         assert np.array_equal(r.scan(), expect), w
 
@@ -208,9 +236,15 @@ def test_batch_rejects_bad_plans():
     with pytest.raises(ac.AcError):
         ac.ac_batch_create([a], np.array([(1 << 32) - 16], np.uint64), np.array([32], np.uint64),
                            np.zeros(1, np.uint32))
+    # the gated plan needs the class gate in every automaton
+    with pytest.raises(ac.AcError):
+        ac.ac_batch_create([p], off, ln, np.zeros(2, np.uint32), tune=tune(algo=ac.AC_ALGO_GATED))
+    with pytest.raises(ac.AcError):
+        ac.ac_batch_create([a], off, ln, np.zeros(2, np.uint32), tune=tune(algo=7))
     # a plan without images falls back to the global table
     b = ac.ac_batch_create([a, g], off, ln, np.array([0, 1], np.uint32))
     assert ac.ac_batch_info(b)["placement"] == ac.AC_PLACE_GLOBAL
+    assert ac.ac_batch_info(b)["algo"] == ac.AC_ALGO_DFA
     d = torch.zeros(64, dtype=torch.uint8, device="cuda")
     out = torch.empty(16, dtype=torch.int64, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
