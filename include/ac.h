@@ -126,6 +126,12 @@ typedef struct {
                               text). Hashed gate: the chance that 6 bytes drawn with
                               the patterns' byte frequencies begin a pattern, plus
                               the filter's false-positive rate */
+    double match_rate;     /* expected matches per text byte, for text whose bytes are
+                              drawn independently with the patterns' own byte
+                              frequencies (0 without a gate). Above 4e-3 the gated
+                              scans stage matches in registers, reserving room in the
+                              match list once per up to 512 matches per wavefront
+                              (else once per up to 64) */
 } ac_info_t;
 
 /*
@@ -192,7 +198,7 @@ enum {
                                 h = X * 0x9E3779 + Y * 0x85EBCB (mod 2^32),
                                 word h >> 17 has bits (h >> 12) & 31 and h & 31
                                 set (empty without this gate) */
-    AC_TABLE_QGATE_TAB = 16   /* uint32 [slots][4], slots a power of two: one entry
+    AC_TABLE_QGATE_TAB = 16,  /* uint32 [slots][4], slots a power of two: one entry
                                 per distinct 6-byte pattern start,
                                 {X | (Y & 255) << 24, Y >> 8 | 1 << 31 | 1 << 30 if
                                 patterns end at the goto state after the 6 bytes,
@@ -201,6 +207,13 @@ enum {
                                 (X * 0xC2B2AF ^ Y * 0x27D4EB) >> (32 - log2 slots)
                                 or slot (X * 0x165667 ^ Y * 0xD3A2E5) >> (32 - log2
                                 slots); unused slots are zero */
+    AC_TABLE_OWN_ONE = 17,    /* uint32 [n_states] (with either gate, else empty): the
+                                id of the one pattern ending exactly at s, or
+                                0xffffffff when none or several do */
+    AC_TABLE_PATH_ONE = 18    /* uint32 [n_states] (class gate, else empty): when
+                                exactly one pattern ends on the path from the root
+                                to s and its id is below 2^28, id | length << 28;
+                                else 0xffffffff */
 };
 
 /*

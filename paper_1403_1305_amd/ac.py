@@ -43,7 +43,8 @@ AC_PAIR_AUTO, AC_PAIR_OFF = 0, 1
 AC_TABLE_DFA, AC_TABLE_GO, AC_TABLE_OUT_OFF, AC_TABLE_OUT_IDS, AC_TABLE_OWN_OFF, \
     AC_TABLE_OWN_IDS, AC_TABLE_HOT_DFA, AC_TABLE_HOT_GO, AC_TABLE_CMAP, AC_TABLE_PAIR, \
     AC_TABLE_GATE_BITS, AC_TABLE_GATE_NODE, AC_TABLE_PATH_OFF, AC_TABLE_PATH_IDS, \
-    AC_TABLE_GATE2_BITS, AC_TABLE_QGATE_BITS, AC_TABLE_QGATE_TAB = range(17)
+    AC_TABLE_GATE2_BITS, AC_TABLE_QGATE_BITS, AC_TABLE_QGATE_TAB, AC_TABLE_OWN_ONE, \
+    AC_TABLE_PATH_ONE = range(19)
 
 _TABLE_DTYPE = {AC_TABLE_HOT_DFA: np.uint16, AC_TABLE_HOT_GO: np.uint16, AC_TABLE_CMAP: np.uint8}
 
@@ -69,7 +70,8 @@ class ac_info_t(ctypes.Structure):
                 ("class_hashed", ctypes.c_uint32), ("table_bytes", ctypes.c_uint64),
                 ("out_entries", ctypes.c_uint64), ("build_ms", ctypes.c_double),
                 ("goto_only", ctypes.c_uint32), ("pair_states", ctypes.c_uint32),
-                ("has_gate", ctypes.c_uint32), ("gate_pass", ctypes.c_double)]
+                ("has_gate", ctypes.c_uint32), ("gate_pass", ctypes.c_double),
+                ("match_rate", ctypes.c_double)]
 
 
 class ac_scan_opts(ctypes.Structure):

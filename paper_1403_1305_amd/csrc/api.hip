@@ -174,6 +174,7 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
     dm.hash_shift = m.hash_shift;
     std::memcpy(dm.hash_letter, m.hash_letter, sizeof(dm.hash_letter));
     dm.gate_pass = m.gate_pass;
+    dm.dense = m.match_rate > acm::kDenseMatches;
     dm.qg_tab_bits = m.qg_tab_bits;
     dm.no_class = m.sigma == 256 ? 0x100u : uint32_t(acm::kNoClass);
     std::vector<uint8_t> cmap(m.cmap, m.cmap + 256);
@@ -184,6 +185,7 @@ int ac_build(const uint8_t *pat_bytes, const uint64_t *pat_off, uint32_t n_patte
         (rc = upload(a, cmap, &dm.cmap, s)) || (rc = upload(a, m.gate_bits, &dm.gate_bits, s)) || (rc = upload(a, m.gate2_bits, &dm.gate2_bits, s)) ||
         (rc = upload(a, m.gate_node, &dm.gate_node, s)) || (rc = upload(a, m.path_off, &dm.path_off, s)) ||
         (rc = upload(a, m.path_ids, &dm.path_ids, s)) || (rc = upload(a, m.pat_len, &dm.pat_len, s)) ||
+        (rc = upload(a, m.path_one, &dm.path_one, s)) || (rc = upload(a, m.own_one, &dm.own_one, s)) ||
         (rc = upload(a, m.qg_bits, &dm.qg_bits, s)) || (rc = upload(a, m.qg_tab, &dm.qg_tab, s))) {
         (void)hipStreamSynchronize(s);
         release(a);
@@ -236,6 +238,7 @@ int ac_info(const ac_automaton *a, ac_info_t *info) {
     info->build_ms = a->m.build_ms;
     info->has_gate = !a->m.gate_bits.empty() ? 1u : !a->m.qg_bits.empty() ? 2u : 0u;
     info->gate_pass = a->m.gate_pass;
+    info->match_rate = a->m.match_rate;
     return AC_OK;
 }
 
@@ -263,6 +266,8 @@ int ac_get_table(const ac_automaton *a, uint32_t which, void *dst, uint64_t dst_
         case AC_TABLE_GATE2_BITS: src = m.gate2_bits.data(); sz = m.gate2_bits.size() * 4; break;
         case AC_TABLE_QGATE_BITS: src = m.qg_bits.data(); sz = m.qg_bits.size() * 4; break;
         case AC_TABLE_QGATE_TAB: src = m.qg_tab.data(); sz = m.qg_tab.size() * 4; break;
+        case AC_TABLE_OWN_ONE: src = m.own_one.data(); sz = m.own_one.size() * 4; break;
+        case AC_TABLE_PATH_ONE: src = m.path_one.data(); sz = m.path_one.size() * 4; break;
         default: return fail(AC_ERR_INVALID, "ac_get_table: unknown table");
     }
     *bytes = sz;

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <string>
+#include <type_traits>
+#include <utility>
 
 #include "../../include/ac.h"
 
@@ -78,10 +80,166 @@ struct Emitter {
         if (n) drain(n);
         if (lane_rank(__ballot(true)) == 0) *qn = 0;
     }
+
+    // flush() for every wave of the workgroup at once, with one atomic for all
+    // of them (called by every thread, every wave having called init; s: LDS,
+    // waves + 2 words): the waves' counts become offsets in s, and thread 0
+    // reserves their total.
+    __device__ __forceinline__ void flush_group(uint32_t *s) {
+        const uint32_t lane = __lane_id(), wave = threadIdx.x / 64u, waves = blockDim.x / 64u;
+        const uint32_t n = *qn;
+        __syncthreads();  // s may alias memory the waves used until now
+        if (lane == 0) s[wave] = n;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t total = 0;
+            for (uint32_t w = 0; w < waves; ++w) {
+                const uint32_t c = s[w];
+                s[w] = total;
+                total += c;
+            }
+            const unsigned long long base = total ? atomicAdd(count, (unsigned long long)total) : 0ull;
+            s[waves] = uint32_t(base);
+            s[waves + 1] = uint32_t(base >> 32);
+        }
+        __syncthreads();
+        const uint64_t base = (uint64_t(s[waves + 1]) << 32 | s[waves]) + s[wave];
+        for (uint32_t i = lane; i < n; i += 64u)
+            if (base + i < cap) out[base + i] = q[i];
+        if (lane == 0) *qn = 0;
+        __syncthreads();  // s may be reused
+    }
 };
 
+// Per-wave match staging in registers, for kernels that call emit with every
+// lane of the wave active: lane l holds queue entries l, l + 64, ..., K of
+// them, so a wave reserves room in the global list (one atomic on its
+// counter, the step whose cost grows with the number of flushes, as every
+// workgroup of the grid updates the same word) once per up to 64 K matches.
+// A call moves the new keys to their queue lanes with one forward permute
+// (a bijection: the keys to lanes n .. n + c - 1, the other lanes' values to
+// the rest).
+template <uint32_t K>
+struct RegEmitter {
+    // The low and high words of the lane's entries. They are updated with
+    // byte permutes: a select written as one, over j, would be turned into a
+    // store at a computed index, which puts the arrays in scratch memory.
+    uint32_t lo_[K], hi_[K];
+    uint32_t n;  // queued keys (the same in every lane)
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+
+    __device__ __forceinline__ void init(uint64_t *out_, uint64_t cap_, unsigned long long *count_) {
+        n = 0;
+        out = out_;
+        cap = cap_;
+        count = count_;
+#pragma unroll
+        for (uint32_t j = 0; j < K; ++j) lo_[j] = hi_[j] = 0;
+    }
+
+    // Write the queued keys to the list and empty the queue.
+    __device__ __forceinline__ void flush() {
+        if (n == 0) return;
+        const uint32_t lane = __lane_id();
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)n);
+        base = (unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(base)) |
+               (unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(base >> 32)) << 32;
+#pragma unroll
+        for (uint32_t j = 0; j < K; ++j) {
+            const uint32_t e = j * 64u + lane;
+            if (e < n && base + e < cap) out[base + e] = uint64_t(hi_[j]) << 32 | lo_[j];
+        }
+        n = 0;
+    }
+
+    // flush() for every wave of the workgroup at once, with one atomic for all
+    // of them (called by every thread; s: LDS, waves + 2 words): the waves'
+    // counts become offsets in s, and thread 0 reserves their total.
+    __device__ __forceinline__ void flush_group(uint32_t *s) {
+        const uint32_t lane = __lane_id(), wave = threadIdx.x / 64u, waves = blockDim.x / 64u;
+        __syncthreads();  // s may alias memory the waves used until now
+        if (lane == 0) s[wave] = n;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t total = 0;
+            for (uint32_t w = 0; w < waves; ++w) {
+                const uint32_t c = s[w];
+                s[w] = total;
+                total += c;
+            }
+            const unsigned long long base = total ? atomicAdd(count, (unsigned long long)total) : 0ull;
+            s[waves] = uint32_t(base);
+            s[waves + 1] = uint32_t(base >> 32);
+        }
+        __syncthreads();
+        const uint64_t base = (uint64_t(s[waves + 1]) << 32 | s[waves]) + s[wave];
+#pragma unroll
+        for (uint32_t j = 0; j < K; ++j) {
+            const uint32_t e = j * 64u + lane;
+            if (e < n && base + e < cap) out[base + e] = uint64_t(hi_[j]) << 32 | lo_[j];
+        }
+        n = 0;
+        __syncthreads();  // s may be reused
+    }
+
+    // Append `key` for every lane with `has`.
+    __device__ __forceinline__ void emit(bool has, uint64_t key) {
+        const uint64_t mask = __ballot(has);
+        if (mask == 0) return;
+        const uint32_t c = uint32_t(__popcll(mask));
+        if (n + c > 64u * K) flush();
+        const uint32_t lane = __lane_id();
+        const uint32_t r = has ? lane_rank(mask) : c + lane_rank(~mask);
+        const int to = int(((n + r) & 63u) << 2);
+        const uint32_t lo = uint32_t(__builtin_amdgcn_ds_permute(to, int(uint32_t(key))));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_ds_permute(to, int(uint32_t(key >> 32))));
+        // this lane received entry n + k when k < c
+        const uint32_t k = (lane - n) & 63u;
+        // its slot: (n + k) >> 6, or none (K) for a lane that received no key
+        const uint32_t s = k < c ? (n + k) >> 6 : K;
+#pragma unroll
+        for (uint32_t j = 0; j < K; ++j) {
+            // perm(x, y, 0x07060504) is x, perm(x, y, 0x03020100) is y
+            const uint32_t sel = s == j ? 0x07060504u : 0x03020100u;
+            lo_[j] = __builtin_amdgcn_perm(lo, lo_[j], sel);
+            hi_[j] = __builtin_amdgcn_perm(hi, hi_[j], sel);
+        }
+        n += c;
+    }
+};
+
+// Workgroup LDS an emitter type needs (for `waves` wavefronts), and its set-up.
+template <class Em>
+struct EmitterLds {
+    static constexpr uint32_t bytes(uint32_t) { return 16; }
+};
+template <>
+struct EmitterLds<Emitter> {
+    static constexpr uint32_t bytes(uint32_t waves) { return waves * kQueueBytesPerWave; }
+};
+__device__ __forceinline__ void init_emitter(Emitter &em, uint8_t *lds, uint64_t *out, uint64_t cap,
+                                             unsigned long long *count) {
+    em.init(lds, out, cap, count);
+}
+template <uint32_t K>
+__device__ __forceinline__ void init_emitter(RegEmitter<K> &em, uint8_t *, uint64_t *out, uint64_t cap,
+                                             unsigned long long *count) {
+    em.init(out, cap, count);
+}
+
+// f(integral_constant<K>) for K = 0, 1, ... while it returns true: a loop
+// unrolled whatever the size of its body.
+template <class F, uint32_t... K>
+__device__ __forceinline__ bool for_each_while(F &&f, std::integer_sequence<uint32_t, K...>) {
+    return (f(std::integral_constant<uint32_t, K>{}) && ...);
+}
+
 // Every pattern id of the set ids[off[s] .. off[s+1]) as a match ending at pos.
-__device__ __forceinline__ void emit_set(Emitter &em, bool has, uint32_t s, uint64_t pos,
+template <class Em>
+__device__ __forceinline__ void emit_set(Em &em, bool has, uint32_t s, uint64_t pos,
                                          const uint32_t *off, const uint32_t *ids) {
     uint32_t k = 0, kend = 0;
     if (has) {

@@ -37,11 +37,13 @@ constexpr uint32_t kLaneBytes = 16;
 constexpr uint32_t kOwnBytes = 63 * kLaneBytes;  // text a wave step owns
 constexpr uint32_t kPrefetch = 4;                // wave steps loaded ahead
 constexpr uint32_t kStartQueue = 125;            // queued start positions per wave: 62 + 63
+constexpr uint32_t kEmitSlots = 8;               // matches queued per lane (a wave flushes up to 512)
+constexpr uint32_t kBatchEmitSlots = 4;          // the same in the batched kernel (fewer registers free)
 constexpr uint32_t kBitmapBytes = kGateCodes / 8;
 constexpr uint32_t kBitmapWords = kGateCodes / 32;
 constexpr uint32_t kBitmap2Words = kGate2Bits / 32;
 constexpr uint32_t kGateLds =
-    kBitmapBytes + kBitmap2Words * 4 + kGateWaves * (kStartQueue * 8 + kQueueBytesPerWave);
+    kBitmapBytes + kBitmap2Words * 4 + kGateWaves * (kStartQueue * 8 + kQueueBytesPerWave) + (kGateWaves + 2) * 4;
 static_assert(kGateLds <= kLdsPerWorkgroup, "gate kernel LDS");
 static_assert(kGateQ == 10 && kGateQ2 == 12, "the window extraction below assumes 10- and 12-byte windows");
 
@@ -52,6 +54,7 @@ struct GateArgs {
     uint32_t shift;           // class of byte b = (b >> shift) & 3
     uint32_t letters;         // byte c = the letter of class c
     const uint32_t *bits, *bits2, *node, *go, *own_off, *own_ids, *path_off, *path_ids, *pat_len;
+    const uint32_t *own_one, *path_one;  // the single pattern of a state or path, or kOneMany
     uint64_t *out;
     uint64_t cap;
     unsigned long long *count;
@@ -108,8 +111,9 @@ __device__ __forceinline__ uint32_t letter_run(const GateArgs &a, const uint32_t
 // on: each step into a state where patterns end reports them at that byte.
 // A walk ends at the first missing edge, a byte outside the alphabet or the
 // end of the text.
+template <class Em>
 __device__ __forceinline__ void walk_on(const GateArgs &a, bool active, uint32_t x, uint32_t i,
-                                        Emitter &em) {
+                                        Em &em) {
     while (__any(active)) {
         uint32_t g = 0;
         if (active) {
@@ -129,32 +133,86 @@ __device__ __forceinline__ void walk_on(const GateArgs &a, bool active, uint32_t
     }
 }
 
-// Walk the start positions p (lanes with `has`), whose window code is `code`:
-// the patterns that end within the window come from the gate table's node,
-// the longer ones from the goto walk beyond it.
-__device__ __forceinline__ void walk_starts(const GateArgs &a, bool has, uint32_t p, uint32_t code,
-                                            Emitter &em) {
-    const uint32_t g = has ? a.node[code] : 0u;
-    const uint32_t d = (g >> kGateNodeBits) & 31u;
-    const uint32_t x = g & kGateNodeMask;
-    uint32_t run = 0;
-    if (has) {
-        uint32_t b[3];
-        load12(a, p, b);
-        run = min(letter_run(a, b), d);
+// The goto entry for byte B at position i from state x (lanes with `active`):
+// 0 past the text's end, for a byte outside the alphabet or a missing edge.
+__device__ __forceinline__ uint32_t go_entry(const GateArgs &a, bool active, uint32_t x, uint32_t B, uint32_t i) {
+    if (!active || i >= a.n) return 0u;
+    const uint32_t c = (B >> a.shift) & 3u;
+    return ((a.letters >> (8u * c)) & 0xffu) == B ? a.go[x * 4u + c] : 0u;
+}
+
+// One step of the walks beyond the window: g is each lane's goto entry for the
+// byte at i (0 once its walk has ended), B1 the byte at i + 1. The state's
+// single pattern and the next goto entry are both requested before the match
+// is reported, so a step waits for one lookup, not three. Returns false once
+// every walk of the wave has ended.
+template <class Em>
+__device__ __forceinline__ bool walk_step(const GateArgs &a, uint32_t &g, uint32_t &x, uint32_t i, uint32_t B1,
+                                          Em &em) {
+    if (!__any(g != 0u)) return false;
+    const bool active = g != 0u;
+    if (active) x = g & kStateMask;
+    const bool acc = active && (g & kAccept);
+    const uint32_t one = acc ? a.own_one[x] : 0u;
+    const uint32_t gn = go_entry(a, active, x, B1, i + 1u);
+    // the patterns ending here: the state's single one, or its list
+    const bool many = acc && one == kOneMany;
+    uint32_t k = 0, ke = acc ? 1u : 0u;
+    if (__any(many) && many) {
+        k = a.own_off[x];
+        ke = a.own_off[x + 1];
     }
-    // patterns ending on the path to x that lie within the letters read
-    const bool hp = has && (g & kGatePathFlag);
-    uint32_t k = hp ? a.path_off[x] : 0u;
-    const uint32_t ke = hp ? a.path_off[x + 1] : 0u;
     while (__any(k < ke)) {
         const bool h = k < ke;
-        const uint32_t id = h ? a.path_ids[k] : 0u;
-        const uint32_t len = h ? a.pat_len[id] : 0u;
+        const uint32_t id = !h ? 0u : many ? a.own_ids[k] : one;
+        em.emit(h, (uint64_t(i + a.base) << 32) | id);
+        k += h ? 1u : 0u;
+    }
+    g = gn;
+    return true;
+}
+
+// Walk the start positions p (lanes with `has`), whose window code is `code`:
+// the patterns that end within the window come from the gate table's node
+// (its single pattern, or its list), the longer ones from the goto walk
+// beyond it. The walk's bytes are loaded a step ahead, so a step waits for
+// its goto lookup alone.
+template <class Em>
+__device__ __forceinline__ void walk_starts(const GateArgs &a, bool has, uint32_t p, uint32_t code,
+                                            Em &em) {
+    const uint32_t e = has ? a.node[code] : 0u;
+    uint32_t b[3] = {0u, 0u, 0u};
+    if (has) load12(a, p, b);
+    const uint32_t d = (e >> kGateNodeBits) & 31u;
+    uint32_t x = e & kGateNodeMask;
+    const uint32_t run = has ? min(letter_run(a, b), d) : 0u;
+    const bool hp = has && (e & kGatePathFlag);
+    const uint32_t one = hp ? a.path_one[x] : kOneMany;
+    const bool deep = has && d == kGateQ && run == kGateQ;
+    static_assert(kGateQ == 10, "bytes 10 and 11 of the start are the last two of b");
+    uint32_t g = go_entry(a, deep, x, (b[2] >> 16) & 0xffu, p + kGateQ);
+    // patterns ending within the window that lie within the letters read:
+    // the path's single one, or its list
+    const bool many = hp && one == kOneMany;
+    uint32_t k = 0, ke = hp ? 1u : 0u;
+    if (__any(many) && many) {
+        k = a.path_off[x];
+        ke = a.path_off[x + 1];
+    }
+    while (__any(k < ke)) {
+        const bool h = k < ke;
+        const uint32_t id = !h ? 0u : many ? a.path_ids[k] : one & 0x0fffffffu;
+        const uint32_t len = !h ? 0u : many ? a.pat_len[id] : one >> 28;
         em.emit(h && len <= run, (uint64_t(p + len - 1 + a.base) << 32) | id);
         k += h ? 1u : 0u;
     }
-    walk_on(a, has && d == kGateQ && run == kGateQ, x, p + kGateQ, em);
+    // the walks beyond the window
+    uint32_t B1 = b[2] >> 24;  // byte 11
+    for (uint32_t i = p + kGateQ;; ++i) {
+        const uint32_t B2 = g != 0u && i + 2u < a.n ? uint32_t(a.text[i + 2u]) : 0u;
+        if (!walk_step(a, g, x, i, B1, em)) break;
+        B1 = B2;
+    }
 }
 
 // Queue entries are {start, classes of the 12 bytes from the start (first
@@ -163,7 +221,8 @@ constexpr uint32_t kNoSecond = 0x80000000u;
 
 // Walk up to 64 of the qn starts queued at q, one per lane; returns how many
 // wait afterwards.
-__device__ __forceinline__ uint32_t drain_starts(const GateArgs &a, const uint2 *q, uint32_t qn, Emitter &em) {
+template <class Em>
+__device__ __forceinline__ uint32_t drain_starts(const GateArgs &a, const uint2 *q, uint32_t qn, Em &em) {
     const uint32_t lane = __lane_id();
     const uint32_t took = min(qn, 64u);
     __builtin_amdgcn_wave_barrier();
@@ -199,18 +258,9 @@ __device__ __forceinline__ uint32_t filter_starts(const uint32_t *s_bits2, uint2
 
 // The windows of one wave step. Lane l (l >= 1) owns the 16 bytes at pos and
 // holds their classes in W; P holds the lane below's (the 16 bytes before),
-// Wn the lane above's. `valid` masks the windows (by their last byte) that
-// lie inside the text. Starts that pass the first level are queued at q with
-// their 12-byte class string (qn queued, the first qf of them already through
-// the second level; the same in every lane). With SECOND the second level
-// applies where the lane holds those 12 bytes. Whenever 63 or more wait (a
-// queue below 63 takes a round's at most 63 new ones) the new ones are
-// filtered, and if 63 or more remain, 64 are walked.
-template <bool SECOND>
-__device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *s_bits, const uint32_t *s_bits2,
-                                             uint32_t W, uint32_t P, uint32_t Wn, uint32_t pos, uint32_t valid,
-                                             uint2 *q, uint32_t &qn, uint32_t &qf, Emitter &em) {
-    const uint32_t lane = __lane_id();
+// Wn the lane above's. Bit j of the result is set when the window ending at
+// the lane's byte j passes the first level.
+__device__ __forceinline__ uint32_t test_windows(const uint32_t *s_bits, uint32_t W, uint32_t P) {
     // window ending at byte j of the lane: classes of bytes j-9 .. j, bits
     // 14 + 2j on in the 64-bit word P:W
     uint32_t m = 0;
@@ -221,12 +271,25 @@ __device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *
         // bit r mod 32 of the word (the field offset takes r's low 5 bits)
         m |= __builtin_amdgcn_ubfe(word, r, 1u) << j;
     }
-    m &= valid;
-    // no LDS read here: the queue takes every start that passed, and the
-    // second level is tested on 64 queued starts at once (filter_starts)
+    return m;
+}
+
+// Queue the starts of the windows in m (as test_windows gives them) at q with
+// their 12-byte class string (qn queued, the first qf of them already through
+// the second level; the same in every lane), taking their bits out of m.
+// With SECOND the second level applies where the lane holds those 12 bytes.
+// Whenever 63 or more wait (a queue below 63 takes a round's at most 63 new
+// ones) the new ones are filtered; if 63 or more remain, it returns false,
+// and the caller walks 64 of them and calls again with what is left in m.
+// There is no LDS read per window: the second level is tested on 64 queued
+// starts at once (filter_starts).
+template <bool SECOND>
+__device__ __forceinline__ bool push_starts(const uint32_t *s_bits2, uint32_t W, uint32_t P, uint32_t Wn,
+                                            uint32_t pos, uint32_t &m, uint2 *q, uint32_t &qn, uint32_t &qf) {
+    const uint32_t lane = __lane_id();
     while (true) {
         const uint64_t has = __ballot(m != 0);
-        if (has == 0) break;
+        if (has == 0) return true;
         if (m) {
             const uint32_t j = uint32_t(__builtin_ctz(m));
             m &= m - 1u;
@@ -239,8 +302,8 @@ __device__ __forceinline__ void step_windows(const GateArgs &a, const uint32_t *
         qn += uint32_t(__popcll(has));
         if (qn >= 63) {
             qn = filter_starts(s_bits2, q, qf, qn);
-            if (qn >= 63) qn = drain_starts(a, q, qn, em);
             qf = qn;
+            if (qn >= 63) return false;
         }
     }
 }
@@ -261,8 +324,9 @@ __device__ __forceinline__ void load_bitmaps(const GateArgs &a, uint32_t *s_bits
 // start of the range is tested, the passing ones walked, and with the text's
 // last tile also the starts too close to its end for a whole window. The
 // wave's queue is empty again on return.
+template <class Em>
 __device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_bits, const uint32_t *s_bits2,
-                                           uint2 *q, Emitter &em, uint32_t t0, uint32_t t1, uint32_t gw,
+                                           uint2 *q, Em &em, uint32_t t0, uint32_t t1, uint32_t gw,
                                            uint32_t W) {
     const uint32_t lane = __lane_id();
     uint32_t qn = 0, qf = 0;  // queued starts, and how many passed the second level (the same in every lane)
@@ -279,21 +343,31 @@ __device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_
     for (uint32_t k = 0; k < kPrefetch; ++k)
         buf[k] = k < cnt ? load_stream(lane_text + (first + k * W) * kOwnBytes - 16) : make_uint4(0u, 0u, 0u, 0u);
     for (uint32_t i = 0; i < cnt; i += kPrefetch) {
-#pragma unroll
-        for (uint32_t k = 0; k < kPrefetch; ++k) {
-            if (i + k >= cnt) break;
-            const uint32_t t = first + (i + k) * W;
-            const uint4 v = buf[k];
-            if (i + k + kPrefetch < cnt) buf[k] = load_stream(lane_text + (t + kPrefetch * W) * kOwnBytes - 16);
-            const uint32_t Wd = pack_classes(v, a.shift);
-            const uint32_t P = __shfl_up(Wd, 1);
-            const uint32_t Wn = __shfl_down(Wd, 1);
-            const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
-            step_windows<true>(a, s_bits, s_bits2, Wd, P, Wn, pos, lane ? 0xffffu : 0u, q, qn, qf, em);
-        }
+        // the ring's entries in turn, each in a register of its own (a fold,
+        // not a loop the compiler may leave rolled and index at run time)
+        for_each_while(
+            [&](auto kc) -> bool {
+                constexpr uint32_t k = decltype(kc)::value;
+                if (i + k >= cnt) return false;
+                const uint32_t t = first + (i + k) * W;
+                const uint4 v = buf[k];
+                if (i + k + kPrefetch < cnt) buf[k] = load_stream(lane_text + (t + kPrefetch * W) * kOwnBytes - 16);
+                const uint32_t Wd = pack_classes(v, a.shift);
+                const uint32_t P = __shfl_up(Wd, 1);
+                const uint32_t Wn = __shfl_down(Wd, 1);
+                const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
+                uint32_t m = lane ? test_windows(s_bits, Wd, P) : 0u;
+                while (!push_starts<true>(s_bits2, Wd, P, Wn, pos, m, q, qn, qf)) {
+                    qn = drain_starts(a, q, qn, em);
+                    qf = qn;
+                }
+                return true;
+            },
+            std::make_integer_sequence<uint32_t, kPrefetch>{});
     }
     // the first tile and a last, partial one, where they lie in the range:
     // loads and windows checked against the text's ends, second level left out
+#pragma unroll 1
     for (uint32_t e = 0; e < 2; ++e) {
         const uint32_t t = e == 0 ? 0u : n_tiles - 1u;
         if (n_tiles == 0 || t < t0 || t >= t1 || (e == 1 && (t < full || t == 0)) || gw != e % W) continue;
@@ -309,7 +383,11 @@ __device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_
             for (uint32_t j = 0; j < 16; ++j)
                 if (base + j >= kGateQ - 1 && base + j < int64_t(a.n)) valid |= 1u << j;
         }
-        step_windows<false>(a, s_bits, s_bits2, Wd, P, Wn, uint32_t(base), valid, q, qn, qf, em);
+        uint32_t me = test_windows(s_bits, Wd, P) & valid;
+        while (!push_starts<false>(s_bits2, Wd, P, Wn, uint32_t(base), me, q, qn, qf)) {
+            qn = drain_starts(a, q, qn, em);
+            qf = qn;
+        }
     }
     qn = filter_starts(s_bits2, q, qf, qn);
     while (qn) qn = drain_starts(a, q, qn, em);
@@ -320,21 +398,23 @@ __device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_
     }
 }
 
+template <class Em>
 __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
     // static LDS: the bitmaps' addresses are then constants the lookups fold in
     __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
     __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
     __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
-    __shared__ __align__(16) uint8_t s_emit[kGateWaves * kQueueBytesPerWave];
+    __shared__ uint32_t s_flush[kGateWaves + 2];
+    __shared__ __align__(16) uint8_t s_emit[EmitterLds<Em>::bytes(kGateWaves)];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    Emitter em;
-    em.init(s_emit, a.out, a.cap, a.count);
+    Em em;
+    init_emitter(em, s_emit, a.out, a.cap, a.count);
     load_bitmaps(a, s_bits, s_bits2);
     __syncthreads();
     const uint32_t n_tiles = uint32_t((uint64_t(a.n) + kOwnBytes - 1) / kOwnBytes);
     gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, 0u, n_tiles,
                blockIdx.x * kGateWaves + wave, gridDim.x * kGateWaves);
-    em.flush();
+    em.flush_group(s_flush);
     complete_launch(a.done, a.count);
 }
 
@@ -342,28 +422,52 @@ __global__ void __launch_bounds__(kGateBlock) gate_kernel(GateArgs a) {
 // take tasks (a range of tiles of one text, and its automaton) in increasing
 // order from a device counter and load an automaton's bitmaps into LDS only
 // when it differs from the previous task's. Tasks are ordered by automaton.
-// Matches go to one list, their end positions in the batch buffer.
 struct BatchLaunch {
-    const uint8_t *text;            // the batch buffer
+    const uint8_t *base;            // task offsets are from here
     const GateTask *tasks;
     uint32_t n_tasks;
     const GateArgs *autos;          // per automaton: tables and class scheme
-    uint64_t *out;
-    uint64_t cap;
-    unsigned long long *count;
+    const GateSink *sinks;          // or NULL: every task writes to `one`
+    GateSink one;
     uint32_t *next_task;            // zero at launch
 };
+
+// After a task whose sink has a completion word: once every wave has written
+// its matches, the total goes to the word and the count back to zero.
+__device__ __forceinline__ void publish_sink(const GateSink &k) {
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    __threadfence();
+    const uint64_t total = __hip_atomic_load(k.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(k.count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(k.word, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(k.word + 1, k.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// *p, the same for the whole workgroup, read a word at a time into scalar
+// registers (a plain copy would hold it in vector registers, which the
+// scan needs).
+__device__ __forceinline__ GateArgs uniform_args(const GateArgs *p) {
+    static_assert(sizeof(GateArgs) % 4 == 0, "GateArgs is read as words");
+    constexpr uint32_t kWords = sizeof(GateArgs) / 4;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t w[kWords];
+#pragma unroll
+    for (uint32_t i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    GateArgs a;
+    memcpy(&a, w, sizeof(GateArgs));
+    return a;
+}
 
 __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
     __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
     __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
     __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
-    __shared__ __align__(16) uint8_t s_emit[kGateWaves * kQueueBytesPerWave];
     __shared__ uint32_t s_task;
+    __shared__ uint32_t s_flush[kGateWaves + 2];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    Emitter em;
-    em.init(s_emit, b.out, b.cap, b.count);
-    uint32_t cur = ~0u;  // automaton whose bitmaps are in LDS
+    RegEmitter<kBatchEmitSlots> em;
+    uint32_t cur = ~0u, sink = ~0u;  // automaton whose bitmaps are in LDS, sink the emitter writes to
     while (true) {
         __syncthreads();  // every wave done with the previous task (and its bitmaps)
         if (threadIdx.x == 0) s_task = atomicAdd(b.next_task, 1u);
@@ -371,22 +475,32 @@ __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
         const uint32_t k = __builtin_amdgcn_readfirstlane(s_task);
         if (k >= b.n_tasks) break;
         const GateTask task = b.tasks[k];
-        GateArgs a = b.autos[task.automaton];
+        GateArgs a = uniform_args(b.autos + task.automaton);
         if (task.automaton != cur) {
             load_bitmaps(a, s_bits, s_bits2);
             __syncthreads();
             cur = task.automaton;
         }
-        a.text = b.text + task.off;
+        const GateSink ks = b.sinks ? b.sinks[task.sink] : b.one;
+        if (task.sink != sink) {
+            if (sink != ~0u) em.flush_group(s_flush);
+            em.init(ks.out, ks.cap, ks.count);
+            sink = task.sink;
+        }
+        a.text = b.base + task.off;
         a.n = task.len;
-        a.base = task.off;
-        a.out = b.out;
-        a.cap = b.cap;
-        a.count = b.count;
+        a.base = task.pos_base;
+        a.out = ks.out;
+        a.cap = ks.cap;
+        a.count = ks.count;
         a.done = Completion{nullptr, nullptr, 0};
         gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, task.t0, task.t1, wave, kGateWaves);
+        if (ks.word) {
+            em.flush_group(s_flush);
+            publish_sink(ks);
+        }
     }
-    em.flush();
+    if (sink != ~0u) em.flush_group(s_flush);
 }
 
 }  // namespace
@@ -409,6 +523,8 @@ GateArgs machine_args(const DeviceMachine &dm) {
     a.path_off = dm.path_off;
     a.path_ids = dm.path_ids;
     a.pat_len = dm.pat_len;
+    a.own_one = dm.own_one;
+    a.path_one = dm.path_one;
     return a;
 }
 
@@ -435,7 +551,8 @@ int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     // one workgroup per CU (the bitmaps fill the LDS), fewer for short texts
     const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
     const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kGateWaves - 1) / kGateWaves, cus)));
-    return launch_kernel(gate_kernel, grid, kGateBlock, 0u, stream, a, err);
+    return dm.dense ? launch_kernel(gate_kernel<RegEmitter<kEmitSlots>>, grid, kGateBlock, 0u, stream, a, err)
+                    : launch_kernel(gate_kernel<Emitter>, grid, kGateBlock, 0u, stream, a, err);
 }
 
 size_t gate_batch_auto_bytes() { return sizeof(GateArgs); }
@@ -447,17 +564,16 @@ void fill_gate_batch_auto(const DeviceMachine &dm, void *dst) {
 
 uint32_t gate_batch_tile_bytes() { return kOwnBytes; }
 
-int launch_gate_batch(const uint8_t *text, const GateTask *tasks, uint32_t n_tasks, const void *autos,
-                      uint64_t *out, uint64_t cap, uint64_t *count, uint32_t *next_task, uint32_t grid,
+int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tasks, const void *autos,
+                      const GateSink *sinks, const GateSink &one, uint32_t *next_task, uint32_t grid,
                       hipStream_t stream, std::string &err) {
     BatchLaunch b{};
-    b.text = text;
+    b.base = base;
     b.tasks = tasks;
     b.n_tasks = n_tasks;
     b.autos = static_cast<const GateArgs *>(autos);
-    b.out = out;
-    b.cap = cap;
-    b.count = reinterpret_cast<unsigned long long *>(count);
+    b.sinks = sinks;
+    b.one = one;
     b.next_task = next_task;
     return launch_kernel(gate_batch_kernel, grid, kGateBlock, 0u, stream, b, err);
 }

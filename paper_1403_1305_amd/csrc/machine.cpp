@@ -3,6 +3,7 @@
 #include "machine.h"
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstring>
 #include <thread>
@@ -149,6 +150,12 @@ void build_gate(Machine &m, const uint8_t *pat, const uint64_t *off) {
     }
     for (uint32_t s = 0; s < S; ++s)
         std::sort(m.path_ids.begin() + m.path_off[s], m.path_ids.begin() + m.path_off[s + 1]);
+    m.path_one.assign(S, kOneMany);
+    for (uint32_t s = 0; s < S; ++s)
+        if (m.path_off[s + 1] - m.path_off[s] == 1) {
+            const uint32_t id = m.path_ids[m.path_off[s]];
+            if (id < (1u << 28)) m.path_one[s] = id | m.pat_len[id] << 28;  // lengths on a path are <= kGateQ
+        }
     uint64_t set = 0;
     for (uint32_t w : m.gate_bits) set += uint32_t(__builtin_popcount(w));
     m.gate_pass = double(set) / double(kGateCodes);
@@ -617,6 +624,8 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
     m.path_off.clear();
     m.path_ids.clear();
     m.pat_len.clear();
+    m.path_one.clear();
+    m.own_one.clear();
     m.qg_bits.clear();
     m.qg_tab.clear();
     m.qg_tab_bits = 0;
@@ -627,6 +636,24 @@ int build_machine(const uint8_t *pat, const uint64_t *off, uint32_t n, const Hot
         uint64_t shortest = ~0ull;
         for (uint32_t k = 0; k < n; ++k) shortest = std::min<uint64_t>(shortest, off[k + 1] - off[k]);
         if (n > 0 && shortest >= kQgQ) build_qgate(m, pat, off);
+    }
+    m.match_rate = 0.0;
+    if (!m.gate_bits.empty() || !m.qg_bits.empty()) {
+        std::vector<double> lf(256, 0.0);  // log byte frequency over the pattern bytes
+        {
+            std::vector<uint64_t> cnt(256, 0);
+            for (uint64_t i = off[0]; i < off[n]; ++i) ++cnt[pat[i]];
+            for (int b = 0; b < 256; ++b)
+                if (cnt[b]) lf[b] = std::log(double(cnt[b]) / double(off[n] - off[0]));
+        }
+        for (uint32_t k = 0; k < n; ++k) {
+            double lp = 0.0;
+            for (uint64_t i = off[k]; i < off[k + 1] && lp > -80.0; ++i) lp += lf[pat[i]];
+            m.match_rate += std::exp(lp);
+        }
+        m.own_one.assign(S, kOneMany);
+        for (uint32_t s = 0; s < S; ++s)
+            if (m.own_off[s + 1] - m.own_off[s] == 1) m.own_one[s] = m.own_ids[m.own_off[s]];
     }
     // 16-bit images are copied as 32-bit words: pad them to whole words
     if (m.hot_dfa.size() & 1) m.hot_dfa.push_back(0);

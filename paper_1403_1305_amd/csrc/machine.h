@@ -39,6 +39,14 @@ constexpr uint32_t kGateCodes = 1u << (2 * kGateQ);
 constexpr uint32_t kGateNodeBits = 26;
 constexpr uint32_t kGateNodeMask = (1u << kGateNodeBits) - 1u;
 constexpr uint32_t kGatePathFlag = 0x80000000u;
+// Expected matches per text byte above which a gated scan stages its matches
+// in registers: fewer reservations in the list, whose counter every
+// workgroup updates, against more registers held. Below it the reservations
+// are spread out enough to overlap with the scan, and the LDS queue's lighter
+// emits win.
+constexpr double kDenseMatches = 4e-3;
+// own_one / path_one: not exactly one pattern (the lists then apply).
+constexpr uint32_t kOneMany = 0xffffffffu;
 // Second gate level: a bitmap of kGate2Bits bits over a hash of the classes
 // of kGateQ2 bytes (the window and the two bytes after it).
 constexpr uint32_t kGateQ2 = kGateQ + 2;
@@ -124,7 +132,13 @@ struct Machine {
     //   gate2_bits kGate2Bits bits: bit gate2_hash(y) is set for every class
     //              string y of kGateQ2 bytes a pattern can begin with (its
     //              first kGateQ2 classes, or every extension of a shorter one);
-    std::vector<uint32_t> gate_bits, gate2_bits, gate_node, path_off, path_ids, pat_len;
+    //   path_one   per state, the one pattern ending on its path when there is
+    //              exactly one and its id is below 2^28: id | length << 28;
+    //              else kOneMany.
+    std::vector<uint32_t> gate_bits, gate2_bits, gate_node, path_off, path_ids, pat_len, path_one;
+    // Per state (built with either gate, else empty): the id of the one
+    // pattern ending exactly at s, kOneMany when none or several do.
+    std::vector<uint32_t> own_one;
     // Hashed gate (empty unless built; never beside the class gate):
     //   qg_bits  kQgWords words, the blocked Bloom filter: for the window
     //            (X, Y) of every pattern's first kQgQ bytes, both bits of
@@ -145,6 +159,11 @@ struct Machine {
     // the chance that a window drawn from the patterns' byte frequencies
     // begins a pattern, plus the filter's false-positive rate.
     double gate_pass = 1.0;
+    // Expected matches per text byte, for text whose bytes are drawn
+    // independently with the patterns' own byte frequencies (the sum over the
+    // patterns of the product of their bytes' frequencies); 0 without a gate.
+    // The gated scans stage matches per lane in registers above kDenseMatches.
+    double match_rate = 0.0;
     double build_ms = 0.0;
 };
 

@@ -42,6 +42,10 @@ constexpr uint32_t kStartQueue = 125;            // queued starts per wave (posi
 constexpr uint32_t kDrainAt = kStartQueue - 63;  // queue length that triggers a drain
 static_assert(kStartQueue <= 64 * kWalks, "a drain takes the whole queue");
 constexpr uint32_t kQgLds = kQgWords * 4 + 256 + kQgWaves * (kStartQueue * 12 + kQueueBytesPerWave);
+// Matches queued per lane: a wave reserves room in the list once per up to
+// 64 times as many.
+constexpr uint32_t kQgEmitSlots = 8;
+using QgEmitter = RegEmitter<kQgEmitSlots>;
 static_assert(kQgLds <= kLdsPerWorkgroup, "hashed gate kernel LDS");
 static_assert(kQgQ == 6, "the window extraction below assumes 6-byte windows");
 
@@ -72,15 +76,15 @@ __device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) { return uin
 // in L2 for that long beats keeping the tables there alone (measured 4%).
 __device__ __forceinline__ uint4 load_stream(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
 
-template <uint32_t... K>
-__device__ __forceinline__ void emit_walks(const QgArgs &a, Emitter &em, const bool (&active)[kWalks],
+template <class Em, uint32_t... K>
+__device__ __forceinline__ void emit_walks(const QgArgs &a, Em &em, const bool (&active)[kWalks],
                                            const uint32_t (&g)[kWalks], const uint32_t (&x)[kWalks],
                                            const uint32_t (&i)[kWalks], std::integer_sequence<uint32_t, K...>) {
     (emit_set(em, active[K] && (g[K] & kAccept), x[K], i[K], a.own_off, a.own_ids), ...);
 }
 
-template <uint32_t... K>
-__device__ __forceinline__ void emit_found(const QgArgs &a, Emitter &em, const bool (&hit)[kWalks],
+template <class Em, uint32_t... K>
+__device__ __forceinline__ void emit_found(const QgArgs &a, Em &em, const bool (&hit)[kWalks],
                                            const uint32_t (&own)[kWalks], const uint32_t (&x)[kWalks],
                                            const uint32_t (&p)[kWalks], std::integer_sequence<uint32_t, K...>) {
     (emit_set(em, hit[K] && own[K], x[K], p[K] + kQgQ - 1u, a.own_off, a.own_ids), ...);
@@ -91,8 +95,9 @@ __device__ __forceinline__ void emit_found(const QgArgs &a, Emitter &em, const b
 // patterns end reports them at that byte. A walk ends at the first missing
 // edge, a byte in no pattern or the end of the text. The walks of a lane
 // advance together, so their loads are in flight at once.
+template <class Em>
 __device__ __forceinline__ void walk_on(const QgArgs &a, const uint8_t *s_cmap, bool (&active)[kWalks],
-                                        uint32_t (&x)[kWalks], uint32_t (&i)[kWalks], Emitter &em) {
+                                        uint32_t (&x)[kWalks], uint32_t (&i)[kWalks], Em &em) {
     while (true) {
         bool any = false;
 #pragma unroll
@@ -128,9 +133,10 @@ __device__ __forceinline__ void walk_on(const QgArgs &a, const uint8_t *s_cmap, 
 // Look up the windows (bytes p .. p + 3 in lo, p + 4 and p + 5 in hi) at the
 // start positions p[k] (those with has[k]; p[k] + kQgQ <= n) in the table
 // and walk on from the states of those found.
+template <class Em>
 __device__ __forceinline__ void walk_starts(const QgArgs &a, const uint8_t *s_cmap, const bool (&has)[kWalks],
                                             const uint32_t (&p)[kWalks], const uint32_t (&lo)[kWalks],
-                                            const uint32_t (&hi)[kWalks], Emitter &em) {
+                                            const uint32_t (&hi)[kWalks], Em &em) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     // the window's two slots; it is in one of them or not in the table
     uint32_t k1[kWalks], sa[kWalks], sb[kWalks];
@@ -181,8 +187,9 @@ struct StartQueue {
 
 // Walk the qn starts queued at q (at most 64 * kWalks), kWalks per lane;
 // returns how many wait afterwards.
+template <class Em>
 __device__ __forceinline__ uint32_t drain_starts(const QgArgs &a, const uint8_t *s_cmap, const StartQueue &q,
-                                                 uint32_t qn, Emitter &em) {
+                                                 uint32_t qn, Em &em) {
     const uint32_t lane = __lane_id();
     const uint32_t took = min(qn, 64u * kWalks);
     bool has[kWalks];
@@ -232,9 +239,10 @@ __device__ __forceinline__ uint32_t test_windows(const uint32_t *s_bits, const u
 // q (qn of them waiting, the same in every lane); whenever kDrainAt or more
 // wait, all are walked (a queue below kDrainAt takes a round's at most 63 new
 // ones, and a drain takes up to 64 * kWalks).
+template <class Em>
 __device__ __forceinline__ void step_windows(const QgArgs &a, const uint32_t *s_bits, const uint8_t *s_cmap,
                                              const uint4 &v, uint32_t P2, uint32_t P3, uint32_t pos, uint32_t valid,
-                                             const StartQueue &q, uint32_t &qn, Emitter &em) {
+                                             const StartQueue &q, uint32_t &qn, Em &em) {
     const uint32_t r[6] = {P2, P3, v.x, v.y, v.z, v.w};
     uint32_t m = test_windows(s_bits, r, std::make_integer_sequence<int, 16>()) & valid;
     while (true) {
@@ -261,15 +269,16 @@ __device__ __forceinline__ void step_windows(const QgArgs &a, const uint32_t *s_
     }
 }
 
+template <class Em>
 __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
     // static LDS: the bitmap's address is then a constant the lookups fold in
     __shared__ __align__(16) uint32_t s_bits[kQgWords];
     __shared__ __align__(16) uint8_t s_cmap[256];
     __shared__ __align__(16) uint32_t s_queue[kQgWaves * kStartQueue * 3];
-    __shared__ __align__(16) uint8_t s_emit[kQgWaves * kQueueBytesPerWave];
+    __shared__ __align__(16) uint8_t s_emit[EmitterLds<Em>::bytes(kQgWaves)];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x & 63u;
-    Emitter em;
-    em.init(s_emit, a.out, a.cap, a.count);
+    Em em;
+    init_emitter(em, s_emit, a.out, a.cap, a.count);
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.bits);
         uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
@@ -294,16 +303,20 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
     for (uint32_t k = 0; k < kPrefetch; ++k)
         buf[k] = k < cnt ? load_stream(lane_text + (first + k * W) * kOwnBytes - 16) : make_uint4(0u, 0u, 0u, 0u);
     for (uint32_t i = 0; i < cnt; i += kPrefetch) {
-#pragma unroll
-        for (uint32_t k = 0; k < kPrefetch; ++k) {
-            if (i + k >= cnt) break;
-            const uint32_t t = first + (i + k) * W;
-            const uint4 v = buf[k];
-            if (i + k + kPrefetch < cnt) buf[k] = load_stream(lane_text + (t + kPrefetch * W) * kOwnBytes - 16);
-            const uint32_t P2 = __shfl_up(v.z, 1), P3 = __shfl_up(v.w, 1);
-            const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
-            step_windows(a, s_bits, s_cmap, v, P2, P3, pos, lane ? 0xffffu : 0u, q, qn, em);
-        }
+        // the ring's entries in turn, each in a register of its own
+        for_each_while(
+            [&](auto kc) -> bool {
+                constexpr uint32_t k = decltype(kc)::value;
+                if (i + k >= cnt) return false;
+                const uint32_t t = first + (i + k) * W;
+                const uint4 v = buf[k];
+                if (i + k + kPrefetch < cnt) buf[k] = load_stream(lane_text + (t + kPrefetch * W) * kOwnBytes - 16);
+                const uint32_t P2 = __shfl_up(v.z, 1), P3 = __shfl_up(v.w, 1);
+                const uint32_t pos = t * kOwnBytes + (lane - 1u) * kLaneBytes;
+                step_windows(a, s_bits, s_cmap, v, P2, P3, pos, lane ? 0xffffu : 0u, q, qn, em);
+                return true;
+            },
+            std::make_integer_sequence<uint32_t, kPrefetch>{});
     }
     // the first tile and a last, partial one: loads and windows checked
     // against the text's ends
@@ -323,7 +336,7 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
         step_windows(a, s_bits, s_cmap, v, P2, P3, uint32_t(base), valid, q, qn, em);
     }
     while (qn) qn = drain_starts(a, s_cmap, q, qn, em);
-    em.flush();
+    em.flush_group(s_queue);  // every queue is empty by now
     complete_launch(a.done, a.count);
 }
 
@@ -362,7 +375,8 @@ int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, 
     // one workgroup per CU (the bitmap fills most of the LDS), fewer for short texts
     const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
     const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kQgWaves - 1) / kQgWaves, cus)));
-    return launch_kernel(qgate_kernel, grid, kQgBlock, 0u, stream, a, err);
+    return dm.dense ? launch_kernel(qgate_kernel<QgEmitter>, grid, kQgBlock, 0u, stream, a, err)
+                    : launch_kernel(qgate_kernel<Emitter>, grid, kQgBlock, 0u, stream, a, err);
 }
 
 }  // namespace acm

@@ -31,11 +31,14 @@ struct DeviceMachine {
     // Start-position gate (Machine::gate_bits and its tables); gate_bits is
     // NULL when the machine has none.
     const uint32_t *gate_bits = nullptr, *gate2_bits = nullptr, *gate_node = nullptr;
-    const uint32_t *path_off = nullptr, *path_ids = nullptr, *pat_len = nullptr;
+    const uint32_t *path_off = nullptr, *path_ids = nullptr, *pat_len = nullptr, *path_one = nullptr;
+    // Machine::own_one (NULL without a gate).
+    const uint32_t *own_one = nullptr;
     // Hashed gate (Machine::qg_bits, qg_tab); qg_bits is NULL without it.
     const uint32_t *qg_bits = nullptr, *qg_tab = nullptr;
     uint32_t qg_tab_bits = 0;
     double gate_pass = 1.0;
+    bool dense = false;  // Machine::match_rate above kDenseMatches: gated scans stage matches in registers
 };
 
 struct ScanConfig {
@@ -94,20 +97,34 @@ inline int launch_gated_scan(const DeviceMachine &dm, const uint8_t *text, uint6
 // Whether launch_gated_scan launches a kernel for n bytes (and so can report
 // a completion).
 inline bool gated_scan_launches(const DeviceMachine &dm, uint64_t n) { return dm.gate_bits ? n > 0 : n >= 6; }
-// The batched gated scan (class gate): a task is tiles [t0, t1) of the text of
-// `len` bytes at byte `off` of the batch buffer (tile t = the start positions
+// The batched gated scan: a task is tiles [t0, t1) of the text of `len` bytes
+// at `off` bytes past the launch's base pointer (tile t = the start positions
 // [1008 t, 1008 t + 1008) of the text), matched against automaton
-// `automaton`; tasks are ordered by automaton. The per-automaton argument
+// `automaton`, its matches reported at end position + pos_base into sink
+// `sink`; tasks are ordered by automaton, and a task whose sink has a
+// completion word is its request's only task. The per-automaton argument
 // blocks (gate_batch_auto_bytes() each, filled by fill_gate_batch_auto) sit
-// in one device array. next_task must be zero at launch.
+// in one device array. The sinks sit in a device array, or (sinks NULL) every
+// task writes to `one`. next_task must be zero at launch.
 struct GateTask {
-    uint32_t off, len, t0, t1, automaton, pad[3];
+    uint64_t off;
+    uint32_t len, t0, t1, automaton, pos_base, sink;
+};
+// Where a task's matches go: the list and its count, and (word != NULL) the
+// completion word that the task's workgroup writes when it has scanned the
+// task: {total, seq}, the total then being cleared for the sink's next use.
+struct GateSink {
+    uint64_t *out;
+    uint64_t cap;
+    unsigned long long *count;
+    uint64_t *word;
+    uint64_t seq;
 };
 size_t gate_batch_auto_bytes();
 void fill_gate_batch_auto(const DeviceMachine &dm, void *dst);
 uint32_t gate_batch_tile_bytes();
-int launch_gate_batch(const uint8_t *text, const GateTask *tasks, uint32_t n_tasks, const void *autos,
-                      uint64_t *out, uint64_t cap, uint64_t *count, uint32_t *next_task, uint32_t grid,
+int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tasks, const void *autos,
+                      const GateSink *sinks, const GateSink &one, uint32_t *next_task, uint32_t grid,
                       hipStream_t stream, std::string &err);
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,

@@ -350,6 +350,7 @@ def test_gate_tables_match_their_definition(seed):
     node = ac.ac_get_table(a, ac.AC_TABLE_GATE_NODE)
     path_off = ac.ac_get_table(a, ac.AC_TABLE_PATH_OFF)
     path_ids = ac.ac_get_table(a, ac.AC_TABLE_PATH_IDS)
+    path_one = ac.ac_get_table(a, ac.AC_TABLE_PATH_ONE)
     go = ac.ac_get_table(a, ac.AC_TABLE_GO).reshape(-1, 4)
     rng = np.random.default_rng(seed + 100)
     codes = np.concatenate([rng.integers(0, 1 << 20, 600), np.nonzero(expect)[0][::61]])
@@ -366,6 +367,12 @@ def test_gate_tables_match_their_definition(seed):
             s = int(go[s, w[i]]) & 0x7FFFFFFF
         assert e & ((1 << 26) - 1) == s, x
         assert path_ids[path_off[s]:path_off[s + 1]].tolist() == prefix_ids, x
+        # the single-pattern shortcut: that pattern and its length, else none
+        one = int(path_one[s])
+        if len(prefix_ids) == 1:
+            assert one == prefix_ids[0] | len(pats[prefix_ids[0]]) << 28, x
+        else:
+            assert one == 0xFFFFFFFF, x
 
 
 @pytest.mark.parametrize("seed", [1, 4])
@@ -413,6 +420,43 @@ def test_gate_only_where_it_applies():
     w = plain_workload("dna256m", n=1 << 20)
     info = ac.ac_info(build_host(w.patterns))
     assert info["has_gate"] == 1 and 0.005 < info["gate_pass"] < 0.02
+
+
+@pytest.mark.parametrize("kind", ["class", "hashed", "none"])
+def test_own_one_names_the_single_pattern_of_a_state(kind):
+    """own_one[s] is the id of the one pattern whose bytes lead from the root
+    to s, and 0xffffffff where none or several do (duplicates), computed here
+    by walking each pattern on the goto function; without a gate the table is
+    empty."""
+    rng = np.random.default_rng(9)
+    if kind == "class":
+        pats = gate_patterns(5)
+    else:
+        a20 = np.frombuffer(PROTEIN, np.uint8)
+        pats = [a20[rng.integers(0, 20, int(L))].tobytes() for L in rng.integers(6, 14, 150)]
+        pats += [pats[4], pats[9] + b"AC"]
+    a = build_host(pats, flags=ac.AC_BUILD_NO_GATE) if kind == "none" else build_host(pats)
+    info = ac.ac_info(a)
+    one = ac.ac_get_table(a, ac.AC_TABLE_OWN_ONE)
+    if kind == "none":
+        assert info["has_gate"] == 0 and ac.ac_get_table(a, ac.AC_TABLE_OWN_ONE).size <= 1
+        return
+    assert info["has_gate"] == (1 if kind == "class" else 2)
+    go = ac.ac_get_table(a, ac.AC_TABLE_GO).reshape(-1, info["n_cols"])
+    cmap = ac.ac_get_table(a, ac.AC_TABLE_CMAP)
+    ends: dict[int, list[int]] = {}
+    for k, p in enumerate(pats):
+        s = 0
+        for b in p:
+            s = int(go[s, cmap[b]]) & 0x7FFFFFFF
+        ends.setdefault(s, []).append(k)
+    assert one.size == info["n_states"]
+    expect = np.full(info["n_states"], 0xFFFFFFFF, np.uint32)
+    for s, ids in ends.items():
+        if len(ids) == 1:
+            expect[s] = ids[0]
+    assert np.array_equal(one, expect)
+    assert any(len(ids) > 1 for ids in ends.values())  # the duplicates took the list path
 
 
 def qgate_window(b: bytes) -> tuple[int, int]:
@@ -488,3 +532,23 @@ def test_hashed_gate_for_the_protein_set():
     w = plain_workload("protein1g", n=1 << 16)
     info = ac.ac_info(build_host(w.patterns))
     assert info["has_gate"] == 2 and 0.02 < info["gate_pass"] < 0.05
+
+
+@pytest.mark.parametrize("kind", ["dna", "protein"])
+def test_match_rate_is_the_expected_matches_per_byte(kind):
+    """ac_info_t.match_rate: for text drawn byte by byte with the patterns' own
+    byte frequencies, the expected number of occurrences starting at a
+    position is the sum over the patterns of the product of their bytes'
+    frequencies (linearity of expectation), computed here from the pattern
+    list; an automaton without a gate reports 0."""
+    rng = np.random.default_rng(21)
+    alphabet = np.frombuffer(DNA if kind == "dna" else PROTEIN, np.uint8)
+    probs = None if kind == "dna" else np.linspace(1.0, 3.0, len(alphabet)) / np.linspace(1.0, 3.0, len(alphabet)).sum()
+    pats = [rng.choice(alphabet, size=int(L), p=probs).tobytes() for L in rng.integers(6, 14, 300)]
+    info = ac.ac_info(build_host(pats))
+    assert info["has_gate"] == (1 if kind == "dna" else 2)
+    allb = np.frombuffer(b"".join(pats), np.uint8)
+    f = np.bincount(allb, minlength=256) / len(allb)
+    expect = sum(float(np.prod(f[np.frombuffer(p, np.uint8)])) for p in pats)
+    assert info["match_rate"] == pytest.approx(expect, rel=1e-9)
+    assert ac.ac_info(build_host(pats, flags=ac.AC_BUILD_NO_GATE))["match_rate"] == 0.0
