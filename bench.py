@@ -68,7 +68,8 @@ PROFILES = {
                                     "paper_1403_1305_amd/csrc/device_common.h",
                                     "paper_1403_1305_amd/csrc/dfa.hip"]),
     "gated": ("gate_scan_dna256m.md", ["paper_1403_1305_amd/csrc/gate.hip",
-                                       "paper_1403_1305_amd/csrc/device_common.h"]),
+                                       "paper_1403_1305_amd/csrc/device_common.h",
+                                       "paper_1403_1305_amd/csrc/machine.h"]),
     "qgated": ("qgate_scan_protein1g.md", ["paper_1403_1305_amd/csrc/qgate.hip",
                                            "paper_1403_1305_amd/csrc/device_common.h",
                                            "paper_1403_1305_amd/csrc/machine.h"]),

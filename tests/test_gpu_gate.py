@@ -129,3 +129,35 @@ def test_auto_picks_the_gate_and_goto_only_builds_scan():
         d, o = ac.patterns_csr(w.patterns)
         n = ac.ac_build(d, o, opts=ac._opts(flags=ac.AC_BUILD_NO_GATE))
         ac.scan_text(n, t, opts=ac._scan_opts(ac.AC_ALGO_GATED))
+
+
+def overflow_case(a, text, expect, cap):
+    """Scan into a list of cap keys: the true count, and cap distinct valid keys."""
+    d = torch.from_numpy(text).to("cuda")
+    out = torch.empty(max(1, cap), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ac.ac_scan(a, d, d.numel(), out, cap, cnt, ac._scan_opts(ac.AC_ALGO_GATED))
+    assert int(cnt.item()) == expect.size
+    got = ac.keys_to_numpy(out[:min(cap, expect.size)]).tolist()
+    assert len(set(got)) == len(got) and set(got) <= set(expect.tolist())
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_both_match_stagings(dense):
+    """Pattern sets on either side of the expected match rate (4e-3 per byte)
+    above which the scan stages matches in registers rather than in the LDS
+    queue: parity on 3 MB of text (thousands of wavefront flushes when
+    dense), then a list a third of the size needed."""
+    rng = np.random.default_rng(41 + dense)
+    pats = rand_patterns(rng, 400, 6, 9) if dense else rand_patterns(rng, 400, 14, 24)
+    pats += pats[:3]  # duplicates: states with several patterns
+    a = build(pats)
+    assert (ac.ac_info(a)["match_rate"] > 4e-3) == dense
+    text = dna_text(3_000_017, 77 + dense)
+    for p in pats[::40]:  # planted occurrences of the long ones too
+        at = int(rng.integers(0, text.size - len(p)))
+        text[at:at + len(p)] = np.frombuffer(p, np.uint8)
+    expect = oracle.oracle_match(text, pats)
+    note("gated stagings", dense, expect.size)
+    assert np.array_equal(gated(a, text), expect)
+    overflow_case(a, text, expect, expect.size // 3)

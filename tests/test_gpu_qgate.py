@@ -172,3 +172,41 @@ def test_auto_picks_the_gate_and_goto_only_builds_scan():
     n = ac.ac_build(d, o, opts=ac._opts(flags=ac.AC_BUILD_NO_GATE))
     with pytest.raises(ac.AcError):
         ac.scan_text(n, t, opts=ac._scan_opts(ac.AC_ALGO_GATED))
+
+
+def overflow_case(a, text, expect, cap):
+    """Scan into a list of cap keys: the true count, and cap distinct valid keys."""
+    d = torch.from_numpy(text).to("cuda")
+    out = torch.empty(max(1, cap), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ac.ac_scan(a, d, d.numel(), out, cap, cnt, ac._scan_opts(ac.AC_ALGO_GATED))
+    assert int(cnt.item()) == expect.size
+    got = ac.keys_to_numpy(out[:min(cap, expect.size)]).tolist()
+    assert len(set(got)) == len(got) and set(got) <= set(expect.tolist())
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_both_match_stagings(dense):
+    """Pattern sets on either side of the expected match rate (4e-3 per byte)
+    above which the scan stages matches in registers rather than in the LDS
+    queue. The dense set uses five letters (no 2-bit class field tells five
+    apart, so the hashed gate applies) and 6-8 byte patterns: parity on 3 MB
+    of text over those letters, then a list a third of the size needed."""
+    rng = np.random.default_rng(51 + dense)
+    if dense:
+        five = np.frombuffer(b"ACDEF", np.uint8)
+        pats = [five[rng.integers(0, 5, int(L))].tobytes() for L in rng.integers(6, 9, 400)]
+        text = five[rng.integers(0, 5, 3_000_017)]
+    else:
+        pats = rand_patterns(rng, 400, 8, 16)
+        text = protein_text(3_000_017, 88)
+    pats += pats[:3]  # duplicates: states with several patterns
+    a = build(pats)
+    assert (ac.ac_info(a)["match_rate"] > 4e-3) == dense
+    for p in pats[::40]:
+        at = int(rng.integers(0, text.size - len(p)))
+        text[at:at + len(p)] = np.frombuffer(p, np.uint8)
+    expect = oracle.oracle_match(text, pats)
+    note("qgate stagings", dense, expect.size)
+    assert np.array_equal(gated(a, text), expect)
+    overflow_case(a, text, expect, expect.size // 3)
