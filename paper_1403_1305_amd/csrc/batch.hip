@@ -27,6 +27,7 @@ struct ac_batch {
     int device = -1;
     bool gated = false;  // the gated plan (tasks of tiles) rather than the DFA's items
     acm::GateTask *d_gtasks = nullptr;
+    bool gate_dense = false;  // some automaton stages its matches in registers
     void *d_gautos = nullptr;  // per automaton: the gated scan's argument block
     uint32_t placement = AC_PLACE_GLOBAL, walkers = 1, block_bytes = 128, chunk = 0;
     uint32_t block = 256, lds = 0, grid = 1;
@@ -104,7 +105,7 @@ int launch(ac_batch *b, const uint8_t *text, uint64_t *out, uint64_t cap, uint64
     if (b->gated) {
         const acm::GateSink one{out, cap, reinterpret_cast<unsigned long long *>(count), nullptr, 0};
         const int rc = acm::launch_gate_batch(text, b->d_gtasks, b->n_tasks, b->d_gautos, nullptr, one, b->d_next,
-                                              b->grid, s, err);
+                                              b->grid, b->gate_dense, s, err);
         return rc == AC_OK ? AC_OK : set_error(rc, err);
     }
     acm::dfa::BatchArgs args{};
@@ -520,8 +521,10 @@ int create_gated(const ac_automaton *const *autos, uint32_t n_autos, const uint6
     } catch (const std::bad_alloc &) {
         return set_error(AC_ERR_NOMEM, "ac_batch_create: out of host memory");
     }
-    for (uint32_t i = 0; i < n_autos; ++i)
+    for (uint32_t i = 0; i < n_autos; ++i) {
         acm::fill_gate_batch_auto(autos[i]->dm, blob.data() + size_t(i) * acm::gate_batch_auto_bytes());
+        b->gate_dense |= autos[i]->dm.dense;
+    }
     b->n_items = b->n_tasks = uint32_t(tasks.size());
     b->grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(grid_max, tasks.size())));
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -459,14 +459,16 @@ __device__ __forceinline__ GateArgs uniform_args(const GateArgs *p) {
     return a;
 }
 
+template <class Em>
 __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
     __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
     __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
     __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
     __shared__ uint32_t s_task;
     __shared__ uint32_t s_flush[kGateWaves + 2];
+    __shared__ __align__(16) uint8_t s_emit[EmitterLds<Em>::bytes(kGateWaves)];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    RegEmitter<kBatchEmitSlots> em;
+    Em em;
     uint32_t cur = ~0u, sink = ~0u;  // automaton whose bitmaps are in LDS, sink the emitter writes to
     while (true) {
         __syncthreads();  // every wave done with the previous task (and its bitmaps)
@@ -484,7 +486,7 @@ __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
         const GateSink ks = b.sinks ? b.sinks[task.sink] : b.one;
         if (task.sink != sink) {
             if (sink != ~0u) em.flush_group(s_flush);
-            em.init(ks.out, ks.cap, ks.count);
+            init_emitter(em, s_emit, ks.out, ks.cap, ks.count);
             sink = task.sink;
         }
         a.text = b.base + task.off;
@@ -566,7 +568,7 @@ uint32_t gate_batch_tile_bytes() { return kOwnBytes; }
 
 int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tasks, const void *autos,
                       const GateSink *sinks, const GateSink &one, uint32_t *next_task, uint32_t grid,
-                      hipStream_t stream, std::string &err) {
+                      bool dense, hipStream_t stream, std::string &err) {
     BatchLaunch b{};
     b.base = base;
     b.tasks = tasks;
@@ -575,7 +577,8 @@ int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tas
     b.sinks = sinks;
     b.one = one;
     b.next_task = next_task;
-    return launch_kernel(gate_batch_kernel, grid, kGateBlock, 0u, stream, b, err);
+    return dense ? launch_kernel(gate_batch_kernel<RegEmitter<kBatchEmitSlots>>, grid, kGateBlock, 0u, stream, b, err)
+                 : launch_kernel(gate_batch_kernel<Emitter>, grid, kGateBlock, 0u, stream, b, err);
 }
 
 }  // namespace acm

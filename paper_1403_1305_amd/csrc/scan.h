@@ -105,7 +105,8 @@ inline bool gated_scan_launches(const DeviceMachine &dm, uint64_t n) { return dm
 // completion word is its request's only task. The per-automaton argument
 // blocks (gate_batch_auto_bytes() each, filled by fill_gate_batch_auto) sit
 // in one device array. The sinks sit in a device array, or (sinks NULL) every
-// task writes to `one`. next_task must be zero at launch.
+// task writes to `one`. next_task must be zero at launch. `dense`: stage the
+// matches in registers (some automaton's DeviceMachine::dense), else in LDS.
 struct GateTask {
     uint64_t off;
     uint32_t len, t0, t1, automaton, pos_base, sink;
@@ -125,7 +126,7 @@ void fill_gate_batch_auto(const DeviceMachine &dm, void *dst);
 uint32_t gate_batch_tile_bytes();
 int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tasks, const void *autos,
                       const GateSink *sinks, const GateSink &one, uint32_t *next_task, uint32_t grid,
-                      hipStream_t stream, std::string &err);
+                      bool dense, hipStream_t stream, std::string &err);
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
                      std::string &err);

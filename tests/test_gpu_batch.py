@@ -136,6 +136,30 @@ def test_gated_batch_reloads_and_long_texts():
         assert np.array_equal(r.scan(), expect), chunk
 
 
+def test_gated_batch_sparse_sets_stage_in_lds():
+    """Pattern sets whose expected match rate is below 4e-3 per byte: the
+    gated batch stages matches in the LDS queue instead of registers. Texts
+    carry planted occurrences so that every queue still flushes."""
+    texts, sets, text_set = batched_workload(n_texts=60, n_sets=5, len_lo_log2=0, len_hi_log2=18,
+                                             set_lo=50, set_hi=2000, pat_lo=14, pat_hi=24, seed=33)
+    rng = np.random.default_rng(33)
+    for t, txt in enumerate(texts):
+        pats = sets[int(text_set[t])]
+        for _ in range(min(40, len(txt) // 64)):
+            p = np.frombuffer(pats[int(rng.integers(len(pats)))], np.uint8)
+            if len(txt) > len(p):
+                at = int(rng.integers(0, len(txt) - len(p)))
+                txt[at:at + len(p)] = p
+    autos = [build(s) for s in sets]
+    assert all(ac.ac_info(a)["match_rate"] < 4e-3 for a in autos)
+    buf, offs, _ = ac.pack_texts(texts)
+    expect = expected(texts, sets, text_set, offs)
+    assert expect.size > 500
+    r = BatchRun(autos, texts, text_set, tune=tune(chunk=2 * 1008, algo=ac.AC_ALGO_GATED))
+    assert r.info["algo"] == ac.AC_ALGO_GATED
+    assert np.array_equal(r.scan(), expect)
+
+
 def test_batch_equals_plain_scans(dna_batch):
     texts, sets, text_set, autos, expect = dna_batch
     r = BatchRun(autos, texts, text_set)
