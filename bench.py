@@ -314,7 +314,7 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     torch.cuda.empty_cache()
 
     budget = 4 << 30
-    srv = ac.Server(autos, hbm_budget=budget, max_inflight=args.slots)
+    srv = ac.Server(autos, hbm_budget=budget, max_inflight=args.slots, max_large=args.max_large)
 
     def replay(arrivals_ns):
         base = srv.now_ns() + 50_000_000  # submissions finish well before the first arrival
@@ -365,6 +365,7 @@ def bench_served(args, torch, ac, stream, rhos=(0.5, 0.8)):
     return {
         "workload": f"served: {SERVED_DESC}", "requests": R, "text_bytes": total, "automata": len(autos),
         "slots": args.slots, "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]), "hbm_budget": budget,
+        "max_large": args.max_large,
         "piece_bytes": 16 << 20,
         "serial_plain": {"value": round(serial_gbs, 3), "unit": "GB/s", "ms": round(serial_ms, 3)},
         "saturated": sat, "poisson": poisson,
@@ -433,6 +434,8 @@ def main():
     p.add_argument("--no-build", action="store_true", help="skip the build-time sub-benchmark")
     p.add_argument("--no-e1", action="store_true", help="skip the 0%%-planted timing check")
     p.add_argument("--slots", type=int, default=SERVE_SLOTS, help="requests a server holds on the device at once")
+    p.add_argument("--max-large", type=int, default=0,
+                   help="served: requests of 4 MiB or more on the device at once (0: no limit)")
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--placement", type=int, default=0)
     p.add_argument("--cpu-sample-mib", type=int, default=256)

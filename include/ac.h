@@ -484,6 +484,12 @@ typedef struct {
                               size match lists until finished requests refine it;
                               0 = 20000. A low guess costs a rescan, never a result. */
     uint32_t flags;        /* reserved, must be 0 */
+    uint32_t max_large;    /* at most this many requests of 4 MiB or more on the device at
+                              once (each fills the GPU by itself); shorter requests are
+                              admitted past one that waits for this. 0 = no limit:
+                              on the served benchmark's mix overlapping them is faster
+                              (2: 690 GB/s, 1: 463, none: 711) */
+    uint32_t reserved;     /* must be 0 */
 } ac_serve_opts;
 
 typedef struct {

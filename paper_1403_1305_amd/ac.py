@@ -97,7 +97,7 @@ class ac_batch_info_t(ctypes.Structure):
 class ac_serve_opts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("piece_bytes", ctypes.c_uint32), ("match_ppm", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("max_large", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class ac_serve_result(ctypes.Structure):
@@ -367,12 +367,12 @@ class Server:
     """Owning handle of an ac_server* (keeps its automata alive)."""
 
     def __init__(self, autos, hbm_budget: int = 0, max_inflight: int = 0, piece_bytes: int = 0,
-                 match_ppm: int = 0, flags: int = 0):
+                 match_ppm: int = 0, flags: int = 0, max_large: int = 0):
         lib = load_library()
         self.autos = list(autos)
         self._texts = {}  # ticket -> the submitted text object, alive until release
         arr = (ctypes.c_void_p * len(self.autos))(*[a.handle for a in self.autos])
-        o = ac_serve_opts(hbm_budget, max_inflight, piece_bytes, match_ppm, flags)
+        o = ac_serve_opts(hbm_budget, max_inflight, piece_bytes, match_ppm, flags, max_large, 0)
         h = _vp()
         _check(lib.ac_serve_create(arr, len(self.autos), ctypes.byref(o), ctypes.byref(h)))
         self.handle = h.value

@@ -505,6 +505,83 @@ __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
     if (sink != ~0u) em.flush_group(s_flush);
 }
 
+// The grouped served launch (requests passed by value, at most kGroupMax).
+struct GroupLaunch {
+    const GateArgs *autos;
+    uint32_t *counters;  // next task, workgroups finished
+    uint32_t n_req, per;
+    GroupReq req[kGroupMax];
+};
+
+template <class Em>
+__global__ void __launch_bounds__(kGateBlock) gate_group_kernel(GroupLaunch g) {
+    __shared__ __align__(16) uint32_t s_bits[kBitmapWords];
+    __shared__ __align__(16) uint32_t s_bits2[kBitmap2Words];
+    __shared__ __align__(16) uint2 s_queue[kGateWaves * kStartQueue];
+    __shared__ uint32_t s_task;
+    __shared__ uint32_t s_flush[kGateWaves + 2];
+    __shared__ __align__(16) uint8_t s_emit[EmitterLds<Em>::bytes(kGateWaves)];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    Em em;
+    uint32_t cur = ~0u;  // automaton whose bitmaps are in LDS
+    uint32_t total = g.req[0].task_end;
+#pragma unroll
+    for (uint32_t i = 1; i < kGroupMax; ++i)
+        if (i < g.n_req) total = g.req[i].task_end;
+    while (true) {
+        __syncthreads();  // every wave done with the previous task (and its bitmaps)
+        if (threadIdx.x == 0) s_task = atomicAdd(g.counters, 1u);
+        __syncthreads();
+        const uint32_t k = __builtin_amdgcn_readfirstlane(s_task);
+        if (k >= total) break;
+        // the task's request, found with fixed indices (the argument block
+        // stays in the kernel-argument segment)
+        GroupReq q = g.req[0];
+        uint32_t first = 0;
+#pragma unroll
+        for (uint32_t i = 1; i < kGroupMax; ++i)
+            if (i < g.n_req && k >= g.req[i - 1].task_end) {
+                q = g.req[i];
+                first = g.req[i - 1].task_end;
+            }
+        const uint32_t tiles = (q.n + kOwnBytes - 1) / kOwnBytes;
+        const uint32_t t0 = (k - first) * g.per, t1 = min(t0 + g.per, tiles);
+        GateArgs a = uniform_args(g.autos + q.automaton);
+        if (q.automaton != cur) {
+            load_bitmaps(a, s_bits, s_bits2);
+            __syncthreads();
+            cur = q.automaton;
+        }
+        a.text = q.text;
+        a.n = q.n;
+        a.base = 0;
+        a.out = q.out;
+        a.cap = q.cap;
+        a.count = q.count;
+        a.done = Completion{nullptr, nullptr, 0};
+        init_emitter(em, s_emit, q.out, q.cap, q.count);
+        gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, t0, t1, wave, kGateWaves);
+        em.flush_group(s_flush);
+        // the request's last task to finish publishes its total
+        if (threadIdx.x == 0) {
+            __threadfence();  // this workgroup's matches and count updates first
+            if (atomicAdd(q.finished, 1u) == q.task_end - first - 1u) {
+                __threadfence();  // the request's other workgroups', seen through the counter
+                const uint64_t n_matches = __hip_atomic_load(q.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(q.count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(q.finished, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(q.word, n_matches, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(q.word + 1, q.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
+    // the launch's last workgroup leaves the counters zero for the next launch
+    if (threadIdx.x == 0 && atomicAdd(g.counters + 1, 1u) == gridDim.x - 1) {
+        __hip_atomic_store(g.counters, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(g.counters + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -579,6 +656,22 @@ int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tas
     b.next_task = next_task;
     return dense ? launch_kernel(gate_batch_kernel<RegEmitter<kBatchEmitSlots>>, grid, kGateBlock, 0u, stream, b, err)
                  : launch_kernel(gate_batch_kernel<Emitter>, grid, kGateBlock, 0u, stream, b, err);
+}
+
+int launch_gate_group(const void *autos, const GroupReq *reqs, uint32_t n_req, uint32_t per,
+                      uint32_t *counters, uint32_t grid, bool dense, hipStream_t stream, std::string &err) {
+    if (n_req == 0 || n_req > kGroupMax || per == 0) {
+        err = "grouped scan: 1 to 16 requests and a task size are needed";
+        return AC_ERR_INVALID;
+    }
+    GroupLaunch g{};
+    g.autos = static_cast<const GateArgs *>(autos);
+    g.counters = counters;
+    g.n_req = n_req;
+    g.per = per;
+    for (uint32_t i = 0; i < n_req; ++i) g.req[i] = reqs[i];
+    return dense ? launch_kernel(gate_group_kernel<RegEmitter<kBatchEmitSlots>>, grid, kGateBlock, 0u, stream, g, err)
+                 : launch_kernel(gate_group_kernel<Emitter>, grid, kGateBlock, 0u, stream, g, err);
 }
 
 }  // namespace acm

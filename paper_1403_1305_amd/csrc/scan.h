@@ -121,6 +121,28 @@ struct GateSink {
     uint64_t *word;
     uint64_t seq;
 };
+// The served form's grouped launch: up to kGroupMax requests, each a text
+// against an automaton with the class gate (its argument block at `automaton`
+// in the same per-automaton array as the batched scan's), cut into tasks of
+// `per` tiles; task_end is the running total of tasks up to and including the
+// request. Each request has its own list, count and completion word: the
+// workgroup that finishes its last task writes {total, seq} to `word` and
+// clears count and finished (both zero before the launch).
+constexpr uint32_t kGroupMax = 16;
+struct GroupReq {
+    const uint8_t *text;
+    uint64_t *out;
+    unsigned long long *count;
+    unsigned int *finished;
+    uint64_t *word;
+    uint64_t cap;
+    uint64_t seq;
+    uint32_t n, automaton, task_end, pad;
+};
+// counters: two words on the device, zero before the first launch on a
+// stream; each launch leaves them zero for the next one on the same stream.
+int launch_gate_group(const void *autos, const GroupReq *reqs, uint32_t n_req, uint32_t per,
+                      uint32_t *counters, uint32_t grid, bool dense, hipStream_t stream, std::string &err);
 size_t gate_batch_auto_bytes();
 void fill_gate_batch_auto(const DeviceMachine &dm, void *dst);
 uint32_t gate_batch_tile_bytes();

@@ -15,8 +15,15 @@
 // scanned in one gated launch (AC_ALGO_GATED); the others with the DFA, in
 // pieces with the state carried on the device from piece to piece (the
 // per-buffer search of the paper's Alg. 1).
+//
+// Short requests against automata with the class gate that one pass of the
+// scheduler issues together share a launch (gate_group_kernel): up to 16
+// requests, cut into tasks of 64 tiles, on one of a few group streams. Each
+// request keeps its own list, count and completion word, written by the
+// workgroup that finishes its last task; its slot's stream is not used.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <new>
@@ -52,6 +59,10 @@ __global__ void zero_slot_kernel(unsigned long long *count, unsigned int *finish
 }
 
 constexpr size_t kSlotWordBytes = 32;
+constexpr uint32_t kGroupStreams = 4;                 // streams that take grouped launches in turn
+constexpr uint64_t kGroupBytes = 4ull << 20;          // requests up to this length may be grouped
+constexpr uint32_t kGroupTiles = 64;                  // tiles of 1,008 start positions per task
+constexpr uint64_t kLargeBytes = 4ull << 20;          // a gated launch this long fills the GPU
 
 class HipDevice final : public Device {
 public:
@@ -69,7 +80,12 @@ public:
     void *words = nullptr;      // device words of every slot (count, two state words, finish counter)
     uint64_t *h_words = nullptr;  // pinned host: two completion words per slot (total, sequence)
     const ac_automaton *autos[acm::serve::kMaxAutos] = {};
+    bool groupable[acm::serve::kMaxAutos] = {};  // gated scan with the class gate
     std::atomic<uint32_t> n_autos{0};
+    void *d_autos = nullptr;       // device: per automaton, the gated scan's argument block
+    uint32_t *d_gcount = nullptr;  // device: two counters per group stream
+    hipStream_t gstream[kGroupStreams] = {};
+    uint32_t next_group = 0;
 
     ~HipDevice() override {
         for (Slot &sl : slots)
@@ -77,6 +93,13 @@ public:
                 (void)hipStreamSynchronize(sl.stream);
                 (void)hipStreamDestroy(sl.stream);
             }
+        for (hipStream_t g : gstream)
+            if (g) {
+                (void)hipStreamSynchronize(g);
+                (void)hipStreamDestroy(g);
+            }
+        if (d_autos) (void)hipFree(d_autos);
+        if (d_gcount) (void)hipFree(d_gcount);
         if (words) (void)hipFree(words);
         if (h_words) (void)hipHostFree(h_words);
         if (pool_base) (void)hipFree(pool_base);
@@ -104,6 +127,11 @@ public:
             sl.d_finished = reinterpret_cast<unsigned int *>(base + 16);
             e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         }
+        if (e == hipSuccess) e = hipMalloc(&d_autos, acm::serve::kMaxAutos * acm::gate_batch_auto_bytes());
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&d_gcount), kGroupStreams * 2 * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(d_gcount, 0, kGroupStreams * 2 * sizeof(uint32_t));
+        for (uint32_t g = 0; g < kGroupStreams && e == hipSuccess; ++g)
+            e = hipStreamCreateWithFlags(&gstream[g], hipStreamNonBlocking);
         return e;
     }
 
@@ -111,9 +139,91 @@ public:
         const uint32_t k = n_autos.load();
         if (k >= acm::serve::kMaxAutos) return false;
         autos[k] = a;
+        groupable[k] = false;
+        if (a->dm.gate_bits && acm::auto_algo(a) == AC_ALGO_GATED) {
+            // the group kernel's argument block (copied before the
+            // automaton can be named by a request)
+            bind_thread();
+            std::vector<uint8_t> blob(acm::gate_batch_auto_bytes());
+            acm::fill_gate_batch_auto(a->dm, blob.data());
+            groupable[k] = hipMemcpy(static_cast<uint8_t *>(d_autos) + size_t(k) * blob.size(), blob.data(),
+                                     blob.size(), hipMemcpyHostToDevice) == hipSuccess;
+        }
         n_autos.store(k + 1);
         *id = k;
         return true;
+    }
+
+    bool grouped(const SlotWork &w) const {
+        return groupable[w.automaton] && w.n > 0 && w.n <= kGroupBytes;
+    }
+
+    // One grouped launch for the items `idx` of w (at most kGroupMax).
+    int run_group(const uint32_t *slot_of, const SlotWork *w, const std::vector<size_t> &idx, std::string &err) {
+        hipStream_t gs = gstream[next_group];
+        uint32_t *counters = d_gcount + 2 * next_group;
+        next_group = (next_group + 1) % kGroupStreams;
+        acm::GroupReq reqs[acm::kGroupMax] = {};
+        uint32_t tasks = 0;
+        bool dense = false;
+        const uint64_t tile = acm::gate_batch_tile_bytes();
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const SlotWork &x = w[idx[j]];
+            const Slot &sl = slots[slot_of[idx[j]]];
+            if (x.src) {
+                const hipError_t e = hipMemcpyAsync(const_cast<uint8_t *>(x.d_text), x.src, x.n, hipMemcpyHostToDevice, gs);
+                if (e != hipSuccess) {
+                    err = std::string("text copy: ") + hipGetErrorString(e);
+                    return AC_ERR_HIP;
+                }
+            }
+            acm::GroupReq &r = reqs[j];
+            r.text = x.d_text;
+            r.out = x.d_out;
+            r.count = sl.d_count;
+            r.finished = sl.d_finished;
+            r.word = h_words + 2 * slot_of[idx[j]];
+            r.cap = x.cap;
+            r.seq = x.seq;
+            r.n = uint32_t(x.n);
+            r.automaton = x.automaton;
+            tasks += uint32_t((x.n + tile * kGroupTiles - 1) / (tile * kGroupTiles));
+            r.task_end = tasks;
+            dense |= autos[x.automaton]->dm.dense;
+        }
+        const uint32_t grid = std::min<uint32_t>(tasks, uint32_t(acm::compute_units(device)));
+        return acm::launch_gate_group(d_autos, reqs, uint32_t(idx.size()), kGroupTiles, counters, grid, dense, gs, err);
+    }
+
+    void run_many(const uint32_t *slot_of, const SlotWork *w, size_t n, uint32_t *pieces,
+                  std::pair<int, std::string> *rc) override {
+        bind_thread();
+        std::vector<size_t> group, rest;
+        for (size_t k = 0; k < n; ++k) (grouped(w[k]) ? group : rest).push_back(k);
+        if (group.size() < 2) {
+            rest.insert(rest.end(), group.begin(), group.end());
+            group.clear();
+        }
+        // by automaton, shortest first: fewer bitmap loads, early completions
+        std::sort(group.begin(), group.end(), [&](size_t x, size_t y) {
+            return w[x].automaton != w[y].automaton ? w[x].automaton < w[y].automaton : w[x].n < w[y].n;
+        });
+        for (size_t b = 0; b < group.size(); b += acm::kGroupMax) {
+            const std::vector<size_t> part(group.begin() + b, group.begin() + std::min(group.size(), b + acm::kGroupMax));
+            std::string err;
+            const int r = run_group(slot_of, w, part, err);
+            for (size_t k : part) {
+                pieces[k] = 1;
+                rc[k].first = r;
+                rc[k].second = err;
+            }
+            if (r != AC_OK)
+                for (size_t k : part) recover(slot_of[k]);
+        }
+        for (size_t k : rest) {
+            rc[k].first = run(slot_of[k], w[k], &pieces[k], rc[k].second);
+            if (rc[k].first != AC_OK) recover(slot_of[k]);
+        }
     }
 
     void bind_thread() {
@@ -185,6 +295,7 @@ public:
         bind_thread();
         Slot &sl = slots[slot];
         (void)hipStreamSynchronize(sl.stream);
+        for (hipStream_t g : gstream) (void)hipStreamSynchronize(g);  // grouped launches write the slot too
         hipLaunchKernelGGL(zero_slot_kernel, dim3(1), dim3(1), 0, sl.stream, sl.d_count, sl.d_finished);
         (void)hipStreamSynchronize(sl.stream);
     }
@@ -228,6 +339,8 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     if (slots > acm::serve::kMaxSlots) return set_error(AC_ERR_INVALID, "ac_serve_create: at most 64 slots");
     if (n_autos > acm::serve::kMaxAutos) return set_error(AC_ERR_INVALID, "ac_serve_create: at most 256 automata");
     if (opts && opts->flags) return set_error(AC_ERR_INVALID, "ac_serve_create: unknown flags");
+    if (opts && opts->reserved) return set_error(AC_ERR_INVALID, "ac_serve_create: reserved must be 0");
+    const uint32_t max_large = opts ? opts->max_large : 0u;  // 0: no limit
 
     ac_server *s = new (std::nothrow) ac_server();
     if (!s) return set_error(AC_ERR_NOMEM, "ac_serve_create: out of host memory");
@@ -248,7 +361,7 @@ int ac_serve_create(const ac_automaton *const *autos, uint32_t n_autos, const ac
     uint32_t id = 0;
     for (uint32_t i = 0; i < n_autos; ++i) d.add(autos[i], &id);
     try {
-        s->sched.reset(new Scheduler(&d, budget, slots, std::vector<double>(n_autos, rate), rate));
+        s->sched.reset(new Scheduler(&d, budget, slots, std::vector<double>(n_autos, rate), rate, kLargeBytes, max_large));
         s->sched->start();
     } catch (...) {
         s->sched.reset();

@@ -142,6 +142,17 @@ public:
     // host memory), never on another slot's work. On an error nothing more
     // of `w` runs, but part of it may still be queued.
     virtual int run(uint32_t slot, const SlotWork &w, uint32_t *pieces, std::string &err) = 0;
+    // Queue the work of several slots at once, as one pass of the scheduler
+    // issues it; the device may give several of them one launch. Per item:
+    // rc[k] as run() returns it (an item that fails has been recovered) and
+    // pieces[k]. By default run() for each.
+    virtual void run_many(const uint32_t *slots, const SlotWork *w, size_t n, uint32_t *pieces,
+                          std::pair<int, std::string> *rc) {
+        for (size_t k = 0; k < n; ++k) {
+            rc[k].first = run(slots[k], w[k], &pieces[k], rc[k].second);
+            if (rc[k].first != AC_OK) recover(slots[k]);
+        }
+    }
     // Non-blocking: true once the slot's work with sequence `seq` is done, with
     // its match total in *count.
     virtual bool done(uint32_t slot, uint64_t seq, uint64_t *count) = 0;
@@ -181,8 +192,13 @@ struct Stats {
 
 class Scheduler {
 public:
-    Scheduler(Device *dev, uint64_t pool_bytes, uint32_t slots, std::vector<double> rates, double rate0)
-        : dev_(dev), slots_(slots, nullptr), rate_(std::move(rates)), rate0_(rate0), t0_(Clock::now()) {
+    // max_large > 0: at most that many requests of large_bytes or more on the
+    // device at once (each fills the chip by itself); shorter ones may pass a
+    // large one that waits for this.
+    Scheduler(Device *dev, uint64_t pool_bytes, uint32_t slots, std::vector<double> rates, double rate0,
+              uint64_t large_bytes = 0, uint32_t max_large = 0)
+        : dev_(dev), slots_(slots, nullptr), rate_(std::move(rates)), rate0_(rate0), t0_(Clock::now()),
+          large_bytes_(large_bytes), max_large_(max_large) {
         pool_.init(pool_bytes);
     }
     ~Scheduler() { stop(); }
@@ -412,10 +428,16 @@ private:
         std::vector<int> free_slots;
         for (size_t i = slots_.size(); i-- > 0;)
             if (!slots_[i]) free_slots.push_back(int(i));
+        uint32_t large = 0;  // large requests holding a slot
+        for (const Request *r : running_) large += is_large(r) ? 1u : 0u;
         auto it = queue_.begin();
         while (it != queue_.end() && !free_slots.empty()) {
             Request *r = *it;
             if (r->t_submit > now) break;  // not arrived yet (the queue is in arrival order)
+            if (is_large(r) && large >= max_large_) {
+                ++it;  // waits for a large one to finish; shorter ones go ahead
+                continue;
+            }
             if (r->n == 0) {
                 r->t_admit = now;
                 r->pieces = 0;
@@ -433,6 +455,7 @@ private:
                 r->phase = Phase::Issuing;
                 r->seq = ++seq_;
                 running_.push_back(r);
+                large += is_large(r) ? 1u : 0u;
                 st_.running_peak = std::max<uint64_t>(st_.running_peak, running_.size());
                 to_issue.push_back(r);
                 it = queue_.erase(it);
@@ -548,10 +571,13 @@ private:
                 lk.unlock();
                 std::vector<std::pair<int, std::string>> rc(work.size());
                 std::vector<uint32_t> pieces(work.size(), 0);
+                std::vector<uint32_t> slots(work.size());
+                std::vector<SlotWork> works(work.size());
                 for (size_t k = 0; k < work.size(); ++k) {
-                    rc[k].first = dev_->run(work[k].slot, work[k].w, &pieces[k], rc[k].second);
-                    if (rc[k].first != AC_OK) dev_->recover(work[k].slot);
+                    slots[k] = work[k].slot;
+                    works[k] = work[k].w;
                 }
+                dev_->run_many(slots.data(), works.data(), work.size(), pieces.data(), rc.data());
                 lk.lock();
                 for (size_t k = 0; k < work.size(); ++k) {
                     Request *r = work[k].r;
@@ -591,6 +617,8 @@ private:
         }
     }
 
+    bool is_large(const Request *r) const { return max_large_ > 0 && r->n >= large_bytes_; }
+
     static constexpr uint64_t kPollNs = 4000;  // completion polling period while work is on the device
 
     Device *dev_;
@@ -599,6 +627,8 @@ private:
     std::vector<double> rate_;  // matches per text byte, per automaton
     double rate0_;
     Clock::time_point t0_;
+    uint64_t large_bytes_;
+    uint32_t max_large_;
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
     std::deque<Request *> queue_;

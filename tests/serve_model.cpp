@@ -30,8 +30,10 @@ uint64_t fake_count(uint32_t automaton, uint64_t n) { return n * (automaton % 4)
 
 class FakeDevice final : public Device {
 public:
-    explicit FakeDevice(uint32_t slots, uint64_t seed, int fail_every)
-        : q_(slots), words_(slots), rng_(seed), fail_every_(fail_every) {
+    // large: requests of this many bytes or more are counted while on the
+    // "device" (large_peak(): the most at once)
+    explicit FakeDevice(uint32_t slots, uint64_t seed, int fail_every, uint64_t large = ~0ull)
+        : q_(slots), words_(slots), rng_(seed), fail_every_(fail_every), large_(large) {
         for (auto &w : words_) {
             w.count.store(0);
             w.seq.store(0);
@@ -64,8 +66,10 @@ public:
         }
         {
             std::lock_guard<std::mutex> g(mu_);
-            q_[slot].push_back(Job{w.seq, fake_count(w.automaton, w.n), delay});
+            const bool large = w.n >= large_;
+            q_[slot].push_back(Job{w.seq, fake_count(w.automaton, w.n), delay, large});
             ++queued_;
+            if (large) large_peak_ = std::max(large_peak_, ++large_now_);
         }
         cv_.notify_all();
         return AC_OK;
@@ -80,10 +84,15 @@ public:
         cv_.wait(lk, [&] { return q_[slot].empty() && !busy_[slot]; });
     }
     uint8_t *pool_at(uint64_t off) override { return reinterpret_cast<uint8_t *>(uintptr_t(0x100000) + off); }
+    uint32_t large_peak() {
+        std::lock_guard<std::mutex> g(mu_);
+        return large_peak_;
+    }
 
 private:
     struct Job {
         uint64_t seq, count, delay_us;
+        bool large;
     };
     struct Word {
         std::atomic<uint64_t> count, seq;
@@ -98,6 +107,9 @@ private:
             busy_[s] = true;
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(j.delay_us));
+            lk.lock();
+            if (j.large) --large_now_;  // before its completion can be seen
+            lk.unlock();
             words_[s].count.store(j.count, std::memory_order_relaxed);
             words_[s].seq.store(j.seq, std::memory_order_release);
             lk.lock();
@@ -113,6 +125,8 @@ private:
     std::vector<std::thread> threads_;
     std::mt19937_64 rng_;
     int fail_every_;
+    uint64_t large_;
+    uint32_t large_now_ = 0, large_peak_ = 0;
     uint64_t queued_ = 0;
     bool stop_ = false;
 };
@@ -218,21 +232,23 @@ int main(int argc, char **argv) {
         s.stats(&st);
         check(st.completed == 80 && st.failed == 0 && st.pool_used == 0, "stats", st.completed, st.failed);
     } else if (scenario == "slots16") {
-        // many small requests over 16 slots, with launch failures injected
-        FakeDevice dev(16, seed, 23);
-        Scheduler s(&dev, 256ull << 20, 16, std::vector<double>(6, 0.02), 0.02);
+        // many small requests over 16 slots, with launch failures injected;
+        // at most 2 of 16 KiB or more on the device at once
+        FakeDevice dev(16, seed, 23, 16 << 10);
+        Scheduler s(&dev, 256ull << 20, 16, std::vector<double>(6, 0.02), 0.02, 16 << 10, 2);
         s.start();
         auto reqs = log_uniform(rng, 600, 16, 1 << 16, 6, true);
         replay(s, reqs, true);
         ac_serve_stats_t st;
         s.stats(&st);
         check(st.completed == 600 && st.pool_used == 0, "stats", st.completed, st.pool_used);
+        check(dev.large_peak() >= 1 && dev.large_peak() <= 2, "large requests at once", dev.large_peak());
     } else if (scenario == "memory") {
         // a 1 MiB budget (admission waits for memory), a match-rate guess far
         // too low (rescans), one list that can never fit, then shutdown while
         // requests wait for memory behind results that are never released
-        FakeDevice dev(4, seed, 0);
-        Scheduler s(&dev, 1 << 20, 4, std::vector<double>(4, 1e-6), 1e-6);
+        FakeDevice dev(4, seed, 0, 8 << 10);
+        Scheduler s(&dev, 1 << 20, 4, std::vector<double>(4, 1e-6), 1e-6, 8 << 10, 1);
         s.start();
         auto reqs = log_uniform(rng, 120, 16, 1 << 16, 4, true);
         // largest first: the first admitted overflow before any finished
@@ -243,6 +259,7 @@ int main(int argc, char **argv) {
         s.stats(&st);
         check(st.rescans > 0, "rescans", st.rescans);
         check(st.pool_peak <= (1u << 20) && st.pool_used == 0, "memory stats", st.pool_peak, st.pool_used);
+        check(dev.large_peak() <= 1, "large requests at once", dev.large_peak());
         // automaton 3 makes n * 3 / 64 keys: 8 MiB of text gives 3 MiB of keys
         uint64_t t = 0;
         std::string err;

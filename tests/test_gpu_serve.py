@@ -263,3 +263,45 @@ def test_close_while_waiting_for_memory():
     tickets = [srv.submit(0, x, on_device=True) for _ in range(6)]
     srv.wait(tickets[0], WAIT_MS)  # held, never released
     srv.close()
+
+
+def test_grouped_short_requests():
+    """Short requests against automata with the class gate that the scheduler
+    issues in one pass share a launch (up to 16 per launch, 64 tiles per
+    task): 48 requests arriving together over 16 slots, from 1 byte to just
+    over the 4 MiB grouping limit (multi-task requests, and one that runs
+    alone), against a sparse and a dense pattern set (the two match
+    stagings), half of them from host memory, with at most one request of
+    4 MiB or more on the device at a time. Every list equals the oracle's,
+    and so does a request run alone afterwards."""
+    rng = np.random.default_rng(77)
+    sets = [rand_patterns(rng, DNA, 2000, 14, 28), rand_patterns(rng, DNA, 400, 6, 9)]
+    autos = [build(s) for s in sets]
+    for a in autos:
+        assert ac.ac_info(a)["has_gate"] == 1 and ac.ac_info(a)["gate_pass"] <= 0.05
+    assert ac.ac_info(autos[0])["match_rate"] < 4e-3 < ac.ac_info(autos[1])["match_rate"]
+    sizes = [1, 9, 10, 17, 1008, 1009, 2016, 64 * 1008, 64 * 1008 + 1, 3 * 64 * 1008 + 5, (4 << 20), (4 << 20) + 16]
+    sizes += [int(x) for x in np.exp(rng.uniform(np.log(16), np.log(1 << 21), 36))]
+    reqs = []
+    for i, n in enumerate(sizes):
+        a = i % 2
+        text = dna_text(n, 800 + i)
+        for _ in range(min(20, n // 64)):  # planted occurrences of the long patterns too
+            p = np.frombuffer(sets[a][int(rng.integers(len(sets[a])))], np.uint8)
+            at = int(rng.integers(0, n - len(p)))
+            text[at:at + len(p)] = p
+        reqs.append((a, text, bool(i % 3)))
+    orc = [oracle.OracleAC(s) for s in sets]
+    expect = [orc[a].scan(t) for a, t, _ in reqs]
+    srv = ac.Server(autos, hbm_budget=512 << 20, max_inflight=16, max_large=1)
+    keep, tickets = submit_all(srv, reqs)
+    got = collect(srv, tickets)
+    for i, ((keys, pieces, _, _), e) in enumerate(zip(got, expect)):
+        note("grouped", i, reqs[i][1].size, e.size)
+        assert np.array_equal(keys, e), i
+        assert pieces == 1, i
+    assert srv.stats()["failed"] == 0
+    keep, (t,) = submit_all(srv, [reqs[5]])
+    (alone,) = collect(srv, [t])
+    assert np.array_equal(alone[0], expect[5])
+    srv.close()
