@@ -610,7 +610,9 @@ GateArgs machine_args(const DeviceMachine &dm) {
 }  // namespace
 
 int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err, const Completion *done) {
+                     uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err, const Completion *done,
+                     uint32_t wave_tiles) {
+    wave_tiles = std::max(1u, wave_tiles);
     if (!dm.gate_bits) {
         err = "ac_scan: this automaton has no start-position gate";
         return AC_ERR_INVALID;
@@ -629,7 +631,7 @@ int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, u
     a.done = done ? *done : Completion{nullptr, nullptr, 0};
     // one workgroup per CU (the bitmaps fill the LDS), fewer for short texts
     const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
-    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kGateWaves - 1) / kGateWaves, cus)));
+    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kGateWaves * wave_tiles - 1) / (kGateWaves * wave_tiles), cus)));
     return dm.dense ? launch_kernel(gate_kernel<RegEmitter<kEmitSlots>>, grid, kGateBlock, 0u, stream, a, err)
                     : launch_kernel(gate_kernel<Emitter>, grid, kGateBlock, 0u, stream, a, err);
 }

@@ -343,7 +343,9 @@ __global__ void __launch_bounds__(kQgBlock) qgate_kernel(QgArgs a) {
 }  // namespace
 
 int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
-                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err, const Completion *done) {
+                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err, const Completion *done,
+                      uint32_t wave_tiles) {
+    wave_tiles = std::max(1u, wave_tiles);
     if (!dm.qg_bits) {
         err = "ac_scan: this automaton has no hashed start-position gate";
         return AC_ERR_INVALID;
@@ -374,7 +376,7 @@ int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, 
     a.done = done ? *done : Completion{nullptr, nullptr, 0};
     // one workgroup per CU (the bitmap fills most of the LDS), fewer for short texts
     const uint64_t tiles = (n + kOwnBytes - 1) / kOwnBytes;
-    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kQgWaves - 1) / kQgWaves, cus)));
+    const uint32_t grid = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>((tiles + kQgWaves * wave_tiles - 1) / (kQgWaves * wave_tiles), cus)));
     return dm.dense ? launch_kernel(qgate_kernel<QgEmitter>, grid, kQgBlock, 0u, stream, a, err)
                     : launch_kernel(qgate_kernel<Emitter>, grid, kQgBlock, 0u, stream, a, err);
 }

@@ -78,21 +78,25 @@ int launch_copy_state(const uint32_t *in, uint32_t *out, hipStream_t stream, std
 // must be set).
 struct Completion;
 // With `done` (n > 0) the launch reports its own completion (device_common.h).
+// wave_tiles: each wavefront takes at least that many 1,008-byte tiles (fewer
+// workgroups for short texts): 1 for the shortest time alone; more where
+// launches run side by side, since every workgroup first loads 136 KiB of
+// bitmaps into LDS.
 int launch_gate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err,
-                     const Completion *done = nullptr);
+                     const Completion *done = nullptr, uint32_t wave_tiles = 1);
 // Failure-less walks from the start positions the hashed gate passes
 // (dm.qg_bits must be set).
 // With `done` (n >= 6) the launch reports its own completion.
 int launch_qgate_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                       uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err,
-                      const Completion *done = nullptr);
+                      const Completion *done = nullptr, uint32_t wave_tiles = 1);
 // The gated scan with whichever gate the machine has.
 inline int launch_gated_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                              uint64_t cap, uint64_t *count, hipStream_t stream, std::string &err,
-                             const Completion *done = nullptr) {
-    return dm.gate_bits ? launch_gate_scan(dm, text, n, out, cap, count, stream, err, done)
-                        : launch_qgate_scan(dm, text, n, out, cap, count, stream, err, done);
+                             const Completion *done = nullptr, uint32_t wave_tiles = 1) {
+    return dm.gate_bits ? launch_gate_scan(dm, text, n, out, cap, count, stream, err, done, wave_tiles)
+                        : launch_qgate_scan(dm, text, n, out, cap, count, stream, err, done, wave_tiles);
 }
 // Whether launch_gated_scan launches a kernel for n bytes (and so can report
 // a completion).

@@ -63,6 +63,10 @@ constexpr uint32_t kGroupStreams = 4;                 // streams that take group
 constexpr uint64_t kGroupBytes = 4ull << 20;          // requests up to this length may be grouped
 constexpr uint32_t kGroupTiles = 64;                  // tiles of 1,008 start positions per task
 constexpr uint64_t kLargeBytes = 4ull << 20;          // a gated launch this long fills the GPU
+// Tiles per wavefront at least, in a request's own gated launch: requests run
+// side by side, so fewer workgroups each (less LDS filling per byte) give
+// more throughput than the shortest time alone would.
+constexpr uint32_t kServeWaveTiles = 8;
 
 class HipDevice final : public Device {
 public:
@@ -254,10 +258,12 @@ public:
             *pieces = 1;
             if (acm::gated_scan_launches(a->dm, w.n)) {
                 const acm::Completion c{sl.d_finished, h_words + 2 * slot, w.seq};
-                rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err, &c);
+                rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err, &c,
+                                            kServeWaveTiles);
                 published = true;
             } else {
-                rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err);
+                rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err, nullptr,
+                                            kServeWaveTiles);
             }
         } else {
             acm::ScanConfig cfg;
