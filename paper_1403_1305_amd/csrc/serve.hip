@@ -66,7 +66,7 @@ constexpr uint64_t kLargeBytes = 4ull << 20;          // a gated launch this lon
 // Tiles per wavefront at least, in a request's own gated launch: requests run
 // side by side, so fewer workgroups each (less LDS filling per byte) give
 // more throughput than the shortest time alone would.
-constexpr uint32_t kServeWaveTiles = 8;
+constexpr uint32_t kServeWaveTiles = 16;
 
 class HipDevice final : public Device {
 public:
