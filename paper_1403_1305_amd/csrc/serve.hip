@@ -18,7 +18,7 @@
 //
 // Short requests against automata with the class gate that one pass of the
 // scheduler issues together share a launch (gate_group_kernel): up to 16
-// requests, cut into tasks of 64 tiles, on one of a few group streams. Each
+// requests, cut into tasks of 256 tiles, on one of a few group streams. Each
 // request keeps its own list, count and completion word, written by the
 // workgroup that finishes its last task; its slot's stream is not used.
 #include <hip/hip_runtime.h>
@@ -61,12 +61,14 @@ __global__ void zero_slot_kernel(unsigned long long *count, unsigned int *finish
 constexpr size_t kSlotWordBytes = 32;
 constexpr uint32_t kGroupStreams = 4;                 // streams that take grouped launches in turn
 constexpr uint64_t kGroupBytes = 4ull << 20;          // requests up to this length may be grouped
-constexpr uint32_t kGroupTiles = 64;                  // tiles of 1,008 start positions per task
 constexpr uint64_t kLargeBytes = 4ull << 20;          // a gated launch this long fills the GPU
 // Tiles per wavefront at least, in a request's own gated launch: requests run
 // side by side, so fewer workgroups each (less LDS filling per byte) give
 // more throughput than the shortest time alone would.
 constexpr uint32_t kServeWaveTiles = 16;
+// Tiles of 1,008 start positions per task of a grouped launch: the same share
+// per wavefront of its 16.
+constexpr uint32_t kGroupTiles = 16 * kServeWaveTiles;
 
 class HipDevice final : public Device {
 public:
