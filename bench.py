@@ -87,6 +87,42 @@ def kernel_source_sha256(kind):
     return h.hexdigest()
 
 
+def pfac_lookups_per_byte(auto, sample):
+    """Goto lookups the failure-less scan makes per text byte: from every
+    start of `sample`, one lookup per byte until a missing edge (or a byte in
+    no pattern), counted on the automaton's host tables."""
+    import numpy as np
+
+    from paper_1403_1305_amd import ac
+
+    go = ac.ac_get_table(auto, ac.AC_TABLE_GO)
+    cols = ac.ac_info(auto)["n_cols"]
+    cmap = ac.ac_get_table(auto, ac.AC_TABLE_CMAP).astype(np.int64)
+    cls = cmap[np.asarray(sample, dtype=np.uint8)]
+    n = len(cls)
+    # all starts advance together: one vectorised lookup per step
+    state = np.zeros(n, dtype=np.int64)
+    pos = np.arange(n, dtype=np.int64)
+    alive = np.ones(n, dtype=bool)
+    lookups = 0
+    while alive.any():
+        idx = np.nonzero(alive)[0]
+        p = pos[idx]
+        ok = p < n
+        idx, p = idx[ok], p[ok]
+        c = cls[p]
+        known = c < cols  # 255 (or 256): a byte in no pattern ends the walk without a lookup
+        lookups += int(known.sum())
+        idx, p, c = idx[known], p[known], c[known]
+        e = go[state[idx] * cols + c]
+        edge = e != 0
+        alive[:] = False
+        alive[idx[edge]] = True
+        state[idx[edge]] = (e[edge] & 0x7FFFFFFF).astype(np.int64)
+        pos[idx[edge]] += 1
+    return round(lookups / n, 3)
+
+
 def profiled_traffic(workload, kind):
     """HBM bytes per scan launch from the committed rocprofv3 counter summary,
     or None when the summary is for another workload or the kernel sources
@@ -591,7 +627,9 @@ def main():
         log("timed pfac")
         pwall, pms = time_steps(pstep, max(3, args.steps // 4), stream, torch, pre=zero)
         pfac = {"value": round(n * len(pms) / pwall / 1e9, 3), "unit": "GB/s",
-                "kernel_ms": round(float(np.mean(pms)), 4), "matches": int(count.item())}
+                "kernel_ms": round(float(np.mean(pms)), 4), "matches": int(count.item()),
+                "lookups_per_byte": pfac_lookups_per_byte(auto, w.text[:1 << 16]),
+                "lookups_per_byte_sample": "every start of the first 64 KiB, on the host goto table"}
 
     # measured streaming-read ceiling: the library's read kernel (the scans'
     # 16-byte non-temporal loads, nothing else) over each text copy
