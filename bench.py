@@ -558,25 +558,31 @@ def main():
     kind = ALGO_NAMES[algo]
     if kind == "gated" and info["has_gate"] == 2:
         kind = "qgated"  # the hashed gate's kernel
-    # append mode: the count is zeroed before each step's first event, so
-    # the events bracket the scan kernel alone (the launch rocprofv3 times)
+    # append mode into a counter of the step's own, zeroed before the timed
+    # region: a step is the scan kernel alone (the launch rocprofv3 times),
+    # which writes the whole match list from its start and counts it
     opts = ac._scan_opts(algo, args.chunk, 0, args.placement, args.walkers, append=1)
     log("headline matcher", kind)
 
     def zero(i):
         count.zero_()
 
+    step_counts = torch.zeros(max(1, args.steps), dtype=torch.int64, device="cuda")
+
     def step(i):
         t = copies[i % 3]
-        ac.ac_scan(auto, t, n, outs, cap, count, opts, stream)
+        ac.ac_scan(auto, t, n, outs, cap, step_counts[i:i + 1], opts, stream)
 
     for i in range(args.warmup):
         zero(i)
-        step(i)
+        ac.ac_scan(auto, copies[i % 3], n, outs, cap, count, opts, stream)
     torch.cuda.synchronize()
     log("timed", kind)
-    wall, ms = time_steps(step, args.steps, stream, torch, pre=zero)
-    matches = int(count.item())
+    wall, ms = time_steps(step, args.steps, stream, torch)
+    per_step = step_counts.cpu().numpy()
+    matches = int(per_step[-1])
+    assert (per_step == matches).all(), "every timed step must report the same match count"
+    count.copy_(step_counts[-1:])
     # the timed list against the oracle's digest of this workload
     golden_ok = None
     gpath = os.path.join(ROOT, "tests", "golden", args.workload + ".json")
