@@ -188,10 +188,12 @@ enum {
     AC_TABLE_PATH_OFF = 12,  /* uint32 [n_states+1]: patterns ending on the path from
                                 the root to s (states of depth <= 10) ... */
     AC_TABLE_PATH_IDS = 13,  /* uint32: ... in PATH_IDS[off[s] .. off[s+1]), ascending */
-    AC_TABLE_GATE2_BITS = 14, /* uint32 [2^11]: second gate level, bit h set for
-                                h = (y * 0x9E3779B1) >> 16 (32-bit product) of every
-                                class string y of 12 bytes (first byte in the lowest
-                                2 bits) that a pattern can begin with */
+    AC_TABLE_GATE2_BITS = 14, /* uint32 [2^11]: second gate level, bits
+                                h = (y * 0x9E3779B1) >> 16 and (y * 0x85EBCA77) >> 16
+                                (32-bit products) set for every class string y of 12
+                                bytes (first byte in the lowest 2 bits) that a
+                                pattern can begin with; a string passes when both of
+                                its bits are set */
     AC_TABLE_QGATE_BITS = 15, /* uint32 [2^15]: hashed gate. For the first 6 bytes
                                 b0..b5 of every pattern, X = b0 | b1 << 8 | b2 << 16,
                                 Y = b3 | b4 << 8 | b5 << 16 and

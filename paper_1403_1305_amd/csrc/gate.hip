@@ -245,8 +245,9 @@ __device__ __forceinline__ uint32_t filter_starts(const uint32_t *s_bits2, uint2
         const uint2 e = lane < t ? q[rd + lane] : make_uint2(0u, 0u);
         bool keep = false;
         if (lane < t) {
-            const uint32_t h = gate2_hash(e.y & 0xffffffu);
-            keep = (e.y & kNoSecond) != 0u || __builtin_amdgcn_ubfe(s_bits2[h >> 5], h, 1u) != 0u;
+            const uint32_t y = e.y & 0xffffffu, h = gate2_hash(y), h2 = gate2_hash2(y);
+            keep = (e.y & kNoSecond) != 0u || (__builtin_amdgcn_ubfe(s_bits2[h >> 5], h, 1u) &
+                                                __builtin_amdgcn_ubfe(s_bits2[h2 >> 5], h2, 1u)) != 0u;
         }
         const uint64_t ks = __ballot(keep);
         __builtin_amdgcn_wave_barrier();

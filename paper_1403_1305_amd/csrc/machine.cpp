@@ -176,8 +176,10 @@ void build_gate(Machine &m, const uint8_t *pat, const uint64_t *off) {
         for (uint32_t i = 0; i < L; ++i) code |= uint32_t(m.cmap[pat[off[k] + i]]) << (2 * i);
         const uint32_t span = 1u << (2 * (kGateQ2 - L));
         for (uint32_t e = 0; e < span; ++e) {
-            const uint32_t h = gate2_hash(code | (L < kGateQ2 ? e << (2 * L) : 0u));
+            const uint32_t y = code | (L < kGateQ2 ? e << (2 * L) : 0u);
+            const uint32_t h = gate2_hash(y), h2 = gate2_hash2(y);
             m.gate2_bits[h >> 5] |= 1u << (h & 31);
+            m.gate2_bits[h2 >> 5] |= 1u << (h2 & 31);
         }
     }
 }

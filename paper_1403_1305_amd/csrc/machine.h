@@ -54,6 +54,10 @@ constexpr uint32_t kGate2Bits = 1u << 16;
 // Bit of the second level for the class string code (first byte in the
 // lowest two bits): the top 16 bits of a multiplicative hash.
 inline constexpr uint32_t gate2_hash(uint32_t code24) { return (code24 * 0x9E3779B1u) >> 16; }
+// The second bit of a class string (two bits per string: a string passes when
+// both are set, which halves the strings that pass by chance at the headline
+// set's fill).
+inline constexpr uint32_t gate2_hash2(uint32_t code24) { return (code24 * 0x85EBCA77u) >> 16; }
 
 // Hashed start-position gate (machines whose patterns are all at least kQgQ
 // bytes long and that have no class gate). A window is the kQgQ bytes from a
@@ -129,9 +133,10 @@ struct Machine {
     //   path_off, path_ids  per node of depth <= kGateQ (CSR over all states),
     //              the patterns ending on its path from the root, ascending;
     //   pat_len    every pattern's length.
-    //   gate2_bits kGate2Bits bits: bit gate2_hash(y) is set for every class
-    //              string y of kGateQ2 bytes a pattern can begin with (its
-    //              first kGateQ2 classes, or every extension of a shorter one);
+    //   gate2_bits kGate2Bits bits: bits gate2_hash(y) and gate2_hash2(y) are
+    //              set for every class string y of kGateQ2 bytes a pattern can
+    //              begin with (its first kGateQ2 classes, or every extension of
+    //              a shorter one);
     //   path_one   per state, the one pattern ending on its path when there is
     //              exactly one and its id is below 2^28: id | length << 28;
     //              else kOneMany.

@@ -391,12 +391,21 @@ def test_second_gate_level_passes_every_pattern_start(seed):
     def h(y):
         return ((y * 0x9E3779B1) & 0xFFFFFFFF) >> 16
 
+    def h2(y):
+        return ((y * 0x85EBCA77) & 0xFFFFFFFF) >> 16
+
     for p in pats:
         c = class_string(p, sh)
         L = min(len(c), 12)
         base = sum(int(c[i]) << (2 * i) for i in range(L))
         for e in range(1 << (2 * (12 - L))):
-            assert bits[h(base | (e << (2 * L)))], (p, e)
+            y = base | (e << (2 * L))
+            assert bits[h(y)] and bits[h2(y)], (p, e)
+    # and strings no pattern begins with mostly fail: both bits set by chance
+    rng2 = np.random.default_rng(seed + 50)
+    ys = rng2.integers(0, 1 << 24, 20000)
+    chance = np.mean([bits[h(int(y))] and bits[h2(int(y))] for y in ys])
+    assert chance < bits.mean() ** 2 * 1.5 + 0.01
     # three 3-byte patterns extend to 3 x 4^9 strings, more than 8 per bit: the level passes all
     everything = build_host([b"ACG", b"TTA", b"GGC"] + pats[:5])
     assert ac.ac_get_table(everything, ac.AC_TABLE_GATE2_BITS).min() == 0xFFFFFFFF
