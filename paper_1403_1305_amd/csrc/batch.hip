@@ -103,8 +103,7 @@ int launch(ac_batch *b, const uint8_t *text, uint64_t *out, uint64_t cap, uint64
     if (e != hipSuccess) return set_error(AC_ERR_HIP, std::string("batch reset launch: ") + hipGetErrorString(e));
     if (b->n_tasks == 0) return AC_OK;
     if (b->gated) {
-        const acm::GateSink one{out, cap, reinterpret_cast<unsigned long long *>(count), nullptr, 0};
-        const int rc = acm::launch_gate_batch(text, b->d_gtasks, b->n_tasks, b->d_gautos, nullptr, one, b->d_next,
+        const int rc = acm::launch_gate_batch(text, b->d_gtasks, b->n_tasks, b->d_gautos, out, cap, count, b->d_next,
                                               b->grid, b->gate_dense, s, err);
         return rc == AC_OK ? AC_OK : set_error(rc, err);
     }
@@ -510,7 +509,6 @@ int create_gated(const ac_automaton *const *autos, uint32_t n_autos, const uint6
                 g.off = text_off[t];
                 g.len = uint32_t(text_len[t]);
                 g.pos_base = uint32_t(text_off[t]);  // end positions in the batch buffer
-                g.sink = 0;
                 g.t0 = uint32_t(t0);
                 g.t1 = uint32_t(std::min(nt, t0 + per));
                 g.automaton = text_auto[t];

@@ -428,22 +428,11 @@ struct BatchLaunch {
     const GateTask *tasks;
     uint32_t n_tasks;
     const GateArgs *autos;          // per automaton: tables and class scheme
-    const GateSink *sinks;          // or NULL: every task writes to `one`
-    GateSink one;
+    uint64_t *out;                  // the batch's one match list
+    uint64_t cap;
+    unsigned long long *count;
     uint32_t *next_task;            // zero at launch
 };
-
-// After a task whose sink has a completion word: once every wave has written
-// its matches, the total goes to the word and the count back to zero.
-__device__ __forceinline__ void publish_sink(const GateSink &k) {
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    __threadfence();
-    const uint64_t total = __hip_atomic_load(k.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(k.count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(k.word, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(k.word + 1, k.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
 
 // *p, the same for the whole workgroup, read a word at a time into scalar
 // registers (a plain copy would hold it in vector registers, which the
@@ -470,7 +459,8 @@ __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
     __shared__ __align__(16) uint8_t s_emit[EmitterLds<Em>::bytes(kGateWaves)];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     Em em;
-    uint32_t cur = ~0u, sink = ~0u;  // automaton whose bitmaps are in LDS, sink the emitter writes to
+    init_emitter(em, s_emit, b.out, b.cap, b.count);
+    uint32_t cur = ~0u;  // automaton whose bitmaps are in LDS
     while (true) {
         __syncthreads();  // every wave done with the previous task (and its bitmaps)
         if (threadIdx.x == 0) s_task = atomicAdd(b.next_task, 1u);
@@ -484,26 +474,16 @@ __global__ void __launch_bounds__(kGateBlock) gate_batch_kernel(BatchLaunch b) {
             __syncthreads();
             cur = task.automaton;
         }
-        const GateSink ks = b.sinks ? b.sinks[task.sink] : b.one;
-        if (task.sink != sink) {
-            if (sink != ~0u) em.flush_group(s_flush);
-            init_emitter(em, s_emit, ks.out, ks.cap, ks.count);
-            sink = task.sink;
-        }
         a.text = b.base + task.off;
         a.n = task.len;
         a.base = task.pos_base;
-        a.out = ks.out;
-        a.cap = ks.cap;
-        a.count = ks.count;
+        a.out = b.out;
+        a.cap = b.cap;
+        a.count = b.count;
         a.done = Completion{nullptr, nullptr, 0};
         gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, task.t0, task.t1, wave, kGateWaves);
-        if (ks.word) {
-            em.flush_group(s_flush);
-            publish_sink(ks);
-        }
     }
-    if (sink != ~0u) em.flush_group(s_flush);
+    em.flush_group(s_flush);
 }
 
 // The grouped served launch (requests passed by value, at most kGroupMax).
@@ -647,15 +627,16 @@ void fill_gate_batch_auto(const DeviceMachine &dm, void *dst) {
 uint32_t gate_batch_tile_bytes() { return kOwnBytes; }
 
 int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tasks, const void *autos,
-                      const GateSink *sinks, const GateSink &one, uint32_t *next_task, uint32_t grid,
+                      uint64_t *out, uint64_t cap, uint64_t *count, uint32_t *next_task, uint32_t grid,
                       bool dense, hipStream_t stream, std::string &err) {
     BatchLaunch b{};
     b.base = base;
     b.tasks = tasks;
     b.n_tasks = n_tasks;
     b.autos = static_cast<const GateArgs *>(autos);
-    b.sinks = sinks;
-    b.one = one;
+    b.out = out;
+    b.cap = cap;
+    b.count = reinterpret_cast<unsigned long long *>(count);
     b.next_task = next_task;
     return dense ? launch_kernel(gate_batch_kernel<RegEmitter<kBatchEmitSlots>>, grid, kGateBlock, 0u, stream, b, err)
                  : launch_kernel(gate_batch_kernel<Emitter>, grid, kGateBlock, 0u, stream, b, err);

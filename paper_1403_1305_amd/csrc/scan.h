@@ -104,26 +104,14 @@ inline bool gated_scan_launches(const DeviceMachine &dm, uint64_t n) { return dm
 // The batched gated scan: a task is tiles [t0, t1) of the text of `len` bytes
 // at `off` bytes past the launch's base pointer (tile t = the start positions
 // [1008 t, 1008 t + 1008) of the text), matched against automaton
-// `automaton`, its matches reported at end position + pos_base into sink
-// `sink`; tasks are ordered by automaton, and a task whose sink has a
-// completion word is its request's only task. The per-automaton argument
-// blocks (gate_batch_auto_bytes() each, filled by fill_gate_batch_auto) sit
-// in one device array. The sinks sit in a device array, or (sinks NULL) every
-// task writes to `one`. next_task must be zero at launch. `dense`: stage the
-// matches in registers (some automaton's DeviceMachine::dense), else in LDS.
+// `automaton`, its matches reported at end position + pos_base into the one
+// list; tasks are ordered by automaton. The per-automaton argument blocks
+// (gate_batch_auto_bytes() each, filled by fill_gate_batch_auto) sit in one
+// device array. next_task must be zero at launch. `dense`: stage the matches
+// in registers (some automaton's DeviceMachine::dense), else in LDS.
 struct GateTask {
     uint64_t off;
-    uint32_t len, t0, t1, automaton, pos_base, sink;
-};
-// Where a task's matches go: the list and its count, and (word != NULL) the
-// completion word that the task's workgroup writes when it has scanned the
-// task: {total, seq}, the total then being cleared for the sink's next use.
-struct GateSink {
-    uint64_t *out;
-    uint64_t cap;
-    unsigned long long *count;
-    uint64_t *word;
-    uint64_t seq;
+    uint32_t len, t0, t1, automaton, pos_base, pad;
 };
 // The served form's grouped launch: up to kGroupMax requests, each a text
 // against an automaton with the class gate (its argument block at `automaton`
@@ -151,7 +139,7 @@ size_t gate_batch_auto_bytes();
 void fill_gate_batch_auto(const DeviceMachine &dm, void *dst);
 uint32_t gate_batch_tile_bytes();
 int launch_gate_batch(const uint8_t *base, const GateTask *tasks, uint32_t n_tasks, const void *autos,
-                      const GateSink *sinks, const GateSink &one, uint32_t *next_task, uint32_t grid,
+                      uint64_t *out, uint64_t cap, uint64_t *count, uint32_t *next_task, uint32_t grid,
                       bool dense, hipStream_t stream, std::string &err);
 int launch_pfac_scan(const DeviceMachine &dm, const uint8_t *text, uint64_t n, uint64_t *out,
                      uint64_t cap, uint64_t *count, const ScanConfig &cfg, hipStream_t stream,
