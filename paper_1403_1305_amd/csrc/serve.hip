@@ -64,8 +64,10 @@ constexpr uint64_t kGroupBytes = 4ull << 20;          // requests up to this len
 constexpr uint64_t kLargeBytes = 4ull << 20;          // a gated launch this long fills the GPU
 // Tiles per wavefront at least, in a request's own gated launch: requests run
 // side by side, so fewer workgroups each (less LDS filling per byte) give
-// more throughput than the shortest time alone would.
+// more throughput than the shortest time alone would. Shorter requests keep
+// more workgroups: with a slot each, their latency bounds the rate.
 constexpr uint32_t kServeWaveTiles = 16;
+constexpr uint32_t kServeWaveTilesShort = 4;
 // Tiles of 1,008 start positions per task of a grouped launch: the same share
 // per wavefront of its 16.
 constexpr uint32_t kGroupTiles = 16 * kServeWaveTiles;
@@ -261,11 +263,11 @@ public:
             if (acm::gated_scan_launches(a->dm, w.n)) {
                 const acm::Completion c{sl.d_finished, h_words + 2 * slot, w.seq};
                 rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err, &c,
-                                            kServeWaveTiles);
+                                            w.n >= kLargeBytes ? kServeWaveTiles : kServeWaveTilesShort);
                 published = true;
             } else {
                 rc = acm::launch_gated_scan(a->dm, w.d_text, w.n, w.d_out, w.cap, count, sl.stream, err, nullptr,
-                                            kServeWaveTiles);
+                                            w.n >= kLargeBytes ? kServeWaveTiles : kServeWaveTilesShort);
             }
         } else {
             acm::ScanConfig cfg;
