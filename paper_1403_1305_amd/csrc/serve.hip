@@ -18,7 +18,7 @@
 //
 // Short requests against automata with the class gate that one pass of the
 // scheduler issues together share a launch (gate_group_kernel): up to 16
-// requests, cut into tasks of 256 tiles, on one of a few group streams. Each
+// requests, cut into tasks of 64 tiles, on one of a few group streams. Each
 // request keeps its own list, count and completion word, written by the
 // workgroup that finishes its last task; its slot's stream is not used.
 #include <hip/hip_runtime.h>
@@ -68,9 +68,9 @@ constexpr uint64_t kLargeBytes = 4ull << 20;          // a gated launch this lon
 // more workgroups: with a slot each, their latency bounds the rate.
 constexpr uint32_t kServeWaveTiles = 16;
 constexpr uint32_t kServeWaveTilesShort = 4;
-// Tiles of 1,008 start positions per task of a grouped launch: the same share
-// per wavefront of its 16.
-constexpr uint32_t kGroupTiles = 16 * kServeWaveTiles;
+// Tiles of 1,008 start positions per task of a grouped launch (its requests
+// are all short): the same share per wavefront of its 16.
+constexpr uint32_t kGroupTiles = 16 * kServeWaveTilesShort;
 
 class HipDevice final : public Device {
 public:

@@ -267,7 +267,7 @@ def test_close_while_waiting_for_memory():
 
 def test_grouped_short_requests():
     """Short requests against automata with the class gate that the scheduler
-    issues in one pass share a launch (up to 16 per launch, 256 tiles per
+    issues in one pass share a launch (up to 16 per launch, 64 tiles per
     task): 48 requests arriving together over 16 slots, from 1 byte to just
     over the 4 MiB grouping limit (multi-task requests, and one that runs
     alone), against a sparse and a dense pattern set (the two match
@@ -280,7 +280,7 @@ def test_grouped_short_requests():
     for a in autos:
         assert ac.ac_info(a)["has_gate"] == 1 and ac.ac_info(a)["gate_pass"] <= 0.05
     assert ac.ac_info(autos[0])["match_rate"] < 4e-3 < ac.ac_info(autos[1])["match_rate"]
-    sizes = [1, 9, 10, 17, 1008, 1009, 2016, 256 * 1008, 256 * 1008 + 1, 3 * 256 * 1008 + 5, (4 << 20), (4 << 20) + 16]
+    sizes = [1, 9, 10, 17, 1008, 1009, 2016, 64 * 1008, 64 * 1008 + 1, 3 * 64 * 1008 + 5, (4 << 20), (4 << 20) + 16]
     sizes += [int(x) for x in np.exp(rng.uniform(np.log(16), np.log(1 << 21), 36))]
     reqs = []
     for i, n in enumerate(sizes):
