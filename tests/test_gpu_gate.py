@@ -160,4 +160,5 @@ def test_both_match_stagings(dense):
     expect = oracle.oracle_match(text, pats)
     note("gated stagings", dense, expect.size)
     assert np.array_equal(gated(a, text), expect)
-    overflow_case(a, text, expect, expect.size // 3)
+    for cap in (0, 1, 5, expect.size // 3):
+        overflow_case(a, text, expect, cap)
