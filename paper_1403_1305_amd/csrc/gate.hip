@@ -367,11 +367,12 @@ __device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_
             std::make_integer_sequence<uint32_t, kPrefetch>{});
     }
     // the first tile and a last, partial one, where they lie in the range:
-    // loads and windows checked against the text's ends, second level left out
+    // loads and windows checked against the text's ends, second level left
+    // out; taken by the last two waves, which have the fewest tiles above
 #pragma unroll 1
     for (uint32_t e = 0; e < 2; ++e) {
         const uint32_t t = e == 0 ? 0u : n_tiles - 1u;
-        if (n_tiles == 0 || t < t0 || t >= t1 || (e == 1 && (t < full || t == 0)) || gw != e % W) continue;
+        if (n_tiles == 0 || t < t0 || t >= t1 || (e == 1 && (t < full || t == 0)) || gw != W - 1 - e % W) continue;
         const int64_t base = int64_t(t) * kOwnBytes - 16 + int64_t(lane) * kLaneBytes;
         const uint4 v = base >= 0 && base < int64_t(a.n) ? *reinterpret_cast<const uint4 *>(a.text + base)
                                                           : make_uint4(0u, 0u, 0u, 0u);
@@ -393,7 +394,8 @@ __device__ __forceinline__ void gate_range(const GateArgs &a, const uint32_t *s_
     qn = filter_starts(s_bits2, q, qf, qn);
     while (qn) qn = drain_starts(a, q, qn, em);
     // starts too close to the end for a whole window: walked from the root
-    if (t1 >= n_tiles && gw == 0) {
+    // (by the last wave, as the last tile)
+    if (t1 >= n_tiles && gw == W - 1) {
         const uint32_t from = a.n > kGateQ - 1 ? a.n - (kGateQ - 1) : 0u;
         walk_on(a, from + lane < a.n, 0u, from + lane, em);
     }
