@@ -162,3 +162,25 @@ def test_both_match_stagings(dense):
     assert np.array_equal(gated(a, text), expect)
     for cap in (0, 1, 5, expect.size // 3):
         overflow_case(a, text, expect, cap)
+
+
+@pytest.mark.parametrize("n8,n_long,seed", [(200, 2000, 0), (400, 6000, 1)])
+def test_many_short_patterns(n8, n_long, seed):
+    """Sets with many 8-byte patterns: each extends to 256 strings of 12
+    classes, so 79% (first set) and 96% (second) of the second gate level's
+    bits are set and most starts the first level passes are walked.
+    The first set's expected match rate is below 4e-3 per byte (LDS
+    staging), the second's above (register staging); both lists equal the
+    oracle's, ragged tail included."""
+    rng = np.random.default_rng(500 + seed)
+    pats = rand_patterns(rng, n8, 8, 8) + rand_patterns(rng, n_long, 12, 32)
+    a = build(pats)
+    bits = np.unpackbits(ac.ac_get_table(a, ac.AC_TABLE_GATE2_BITS).view(np.uint8))
+    assert bits.mean() > 0.5
+    assert (ac.ac_info(a)["match_rate"] > 4e-3) == bool(seed)
+    text = dna_text((3 << 20) + 12345 + seed, 600 + seed)
+    expect = oracle.oracle_match(text, pats)
+    assert expect.size > 5000
+    note("many short patterns", n8, n_long, text.size, expect.size)
+    assert np.array_equal(gated(a, text), expect)
+
