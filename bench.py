@@ -8,8 +8,8 @@ already resident in HBM. Three copies of the text are scanned in rotation so
 that no step can be served from the previous step's cache contents (3 x 256
 MiB exceeds the 256 MB MALL). Machine construction, the device sort of the
 match list, the chunked full-DFA scan and the failure-less (PFAC) kernel are
-timed separately and reported beside the headline, as are the batched and
-served forms.
+timed separately and reported beside the headline, as are the 1 GiB protein
+configuration and the batched and served forms.
 
 Prints one JSON line (see the keys below).
 """
