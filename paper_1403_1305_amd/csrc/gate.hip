@@ -436,18 +436,50 @@ struct BatchLaunch {
     uint32_t *next_task;            // zero at launch
 };
 
-// *p, the same for the whole workgroup, read a word at a time into scalar
-// registers (a plain copy would hold it in vector registers, which the
-// scan needs).
+// A value the same in every lane, in scalar registers.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+    return uint64_t(uniform_u32(uint32_t(x))) | uint64_t(uniform_u32(uint32_t(x >> 32))) << 32;
+}
+// A pointer to global memory, the same in every lane. One loaded from memory
+// (not a kernel argument) has no known address space, and the compiler would
+// reach it with flat loads, whose waits also take in the LDS reads in flight;
+// the cast lets it use global loads.
+template <class T>
+__device__ __forceinline__ T *uniform_global(T *p) {
+    const uint64_t u = uniform_u64(reinterpret_cast<uint64_t>(p));
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (T *)(__attribute__((address_space(1))) T *)u;
+#else
+    return reinterpret_cast<T *>(u);
+#endif
+}
+
+// *p, the same for the whole workgroup, field by field into scalar registers
+// (a plain copy would hold it in vector registers, which the scan needs).
 __device__ __forceinline__ GateArgs uniform_args(const GateArgs *p) {
-    static_assert(sizeof(GateArgs) % 4 == 0, "GateArgs is read as words");
-    constexpr uint32_t kWords = sizeof(GateArgs) / 4;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
-    uint32_t w[kWords];
-#pragma unroll
-    for (uint32_t i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    const GateArgs s = *p;
     GateArgs a;
-    memcpy(&a, w, sizeof(GateArgs));
+    a.text = uniform_global(s.text);
+    a.n = uniform_u32(s.n);
+    a.base = uniform_u32(s.base);
+    a.shift = uniform_u32(s.shift);
+    a.letters = uniform_u32(s.letters);
+    a.bits = uniform_global(s.bits);
+    a.bits2 = uniform_global(s.bits2);
+    a.node = uniform_global(s.node);
+    a.go = uniform_global(s.go);
+    a.own_off = uniform_global(s.own_off);
+    a.own_ids = uniform_global(s.own_ids);
+    a.path_off = uniform_global(s.path_off);
+    a.path_ids = uniform_global(s.path_ids);
+    a.pat_len = uniform_global(s.pat_len);
+    a.own_one = uniform_global(s.own_one);
+    a.path_one = uniform_global(s.path_one);
+    a.out = uniform_global(s.out);
+    a.cap = uniform_u64(s.cap);
+    a.count = uniform_global(s.count);
+    a.done = Completion{uniform_global(s.done.finished), uniform_global(s.done.word), uniform_u64(s.done.seq)};
     return a;
 }
 
@@ -535,14 +567,14 @@ __global__ void __launch_bounds__(kGateBlock) gate_group_kernel(GroupLaunch g) {
             __syncthreads();
             cur = q.automaton;
         }
-        a.text = q.text;
+        a.text = uniform_global(q.text);
         a.n = q.n;
         a.base = 0;
-        a.out = q.out;
+        a.out = uniform_global(q.out);
         a.cap = q.cap;
-        a.count = q.count;
+        a.count = uniform_global(q.count);
         a.done = Completion{nullptr, nullptr, 0};
-        init_emitter(em, s_emit, q.out, q.cap, q.count);
+        init_emitter(em, s_emit, a.out, a.cap, a.count);
         gate_range(a, s_bits, s_bits2, s_queue + wave * kStartQueue, em, t0, t1, wave, kGateWaves);
         em.flush_group(s_flush);
         // the request's last task to finish publishes its total
